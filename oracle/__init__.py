@@ -1,0 +1,227 @@
+"""Plain FP64 CPU oracle of the split second-order Godunov sweep.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code with
+the HIP library: the C source here (``hydro_oracle.c``, ``mlp_oracle.c``) is
+compiled by ``oracle/build.py`` with gcc into ``liboracle.so`` and reached through
+ctypes on host numpy arrays.
+
+The method follows the paper's statement (Section 1; Figures 1, 2 and 5): a
+directionally split, second-order Godunov scheme for the 2D compressible Euler
+equations on a fixed rectangular grid, with a Riemann problem at every interface.
+The readings taken where the paper is silent are listed in ``hydro_oracle.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BC_REFLECT, BC_OUTFLOW, BC_PERIODIC = 1, 2, 3
+DIR_X, DIR_Y = 0, 1
+RHO_MIN = 1e-10
+C_MIN = 1e-10
+
+
+class Cfg(ctypes.Structure):
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("bc", ctypes.c_int),
+        ("niter", ctypes.c_int),
+        ("tol", ctypes.c_double),
+    ]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_LL = ctypes.POINTER(ctypes.c_longlong)
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "oracle_cons_to_prim": (None, [_D, ctypes.c_double, _D]),
+        "oracle_p_floor": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
+        "oracle_sound_speed": (ctypes.c_double, [_D, ctypes.c_double]),
+        "oracle_minmod": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
+        "oracle_trace": (None, [_D, _D, ctypes.c_double, ctypes.c_double, _D, _D]),
+        "oracle_ptr_guess": (ctypes.c_double, [_D, _D, ctypes.c_double]),
+        "oracle_two_shock_f": (ctypes.c_double, [_D, _D, ctypes.c_double, ctypes.c_double]),
+        "oracle_riemann": (
+            ctypes.c_int,
+            [_D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D, _D,
+             ctypes.POINTER(ctypes.c_int)],
+        ),
+        "oracle_flux": (None, [_D, ctypes.c_double, _D]),
+        "oracle_pencil": (None, [_D, ctypes.c_int, ctypes.c_double, ctypes.POINTER(Cfg), _LL]),
+        "oracle_load_pencil": (
+            None,
+            [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D],
+        ),
+        "oracle_sweep": (
+            None,
+            [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+             ctypes.POINTER(Cfg), _LL],
+        ),
+        "oracle_max_speed": (ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+        "oracle_compute_dt": (
+            ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg)]),
+        "oracle_step": (
+            ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg), _LL]),
+        "oracle_totals": (None, [_D, ctypes.c_int, ctypes.c_int, _D]),
+        "oracle_threads": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _vec(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(4))
+
+
+def cfg(gamma=1.4, cfl=0.8, bc=BC_PERIODIC, niter=10, tol=1e-8) -> Cfg:
+    return Cfg(float(gamma), float(cfl), int(bc), int(niter), float(tol))
+
+
+# ---------------------------------------------------------------- single steps
+def cons_to_prim(u, gamma=1.4) -> np.ndarray:
+    u = _vec(u)
+    q = np.zeros(4)
+    _load().oracle_cons_to_prim(_dptr(u), gamma, _dptr(q))
+    return q
+
+
+def p_floor(rho, gamma=1.4) -> float:
+    return _load().oracle_p_floor(float(rho), float(gamma))
+
+
+def sound_speed(q, gamma=1.4) -> float:
+    q = _vec(q)
+    return _load().oracle_sound_speed(_dptr(q), gamma)
+
+
+def minmod(a, b) -> float:
+    return _load().oracle_minmod(float(a), float(b))
+
+
+def trace(q, dq, gamma, lam):
+    q, dq = _vec(q), _vec(dq)
+    qm, qp = np.zeros(4), np.zeros(4)
+    _load().oracle_trace(_dptr(q), _dptr(dq), gamma, lam, _dptr(qm), _dptr(qp))
+    return qm, qp
+
+
+def ptr_guess(qL, qR, gamma=1.4) -> float:
+    qL, qR = _vec(qL), _vec(qR)
+    return _load().oracle_ptr_guess(_dptr(qL), _dptr(qR), gamma)
+
+
+def two_shock_f(qL, qR, gamma, p) -> float:
+    qL, qR = _vec(qL), _vec(qR)
+    return _load().oracle_two_shock_f(_dptr(qL), _dptr(qR), gamma, float(p))
+
+
+def riemann(qL, qR, gamma=1.4, niter=10, tol=1e-8):
+    """Returns (godunov_state[4], pstar, ustar, iterations, converged)."""
+    qL, qR = _vec(qL), _vec(qR)
+    qg = np.zeros(4)
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    conv = ctypes.c_int()
+    it = _load().oracle_riemann(_dptr(qL), _dptr(qR), gamma, niter, tol, _dptr(qg),
+                                ctypes.byref(ps), ctypes.byref(us), ctypes.byref(conv))
+    return qg, ps.value, us.value, it, bool(conv.value)
+
+
+def flux(qg, gamma=1.4) -> np.ndarray:
+    qg = _vec(qg)
+    F = np.zeros(4)
+    _load().oracle_flux(_dptr(qg), gamma, _dptr(F))
+    return F
+
+
+# ---------------------------------------------------------------- pencils, grids
+def pencil(w: np.ndarray, lam: float, c: Cfg, hist: np.ndarray | None = None) -> np.ndarray:
+    """1D update of a pencil held with its ghosts, w of shape [4, n+4]; returns
+    the updated copy."""
+    w = np.ascontiguousarray(w, dtype=np.float64).copy()
+    n = w.shape[1] - 4
+    hp = hist.ctypes.data_as(_LL) if hist is not None else None
+    _load().oracle_pencil(_dptr(w), n, lam, ctypes.byref(c), hp)
+    return w
+
+
+def load_pencil(U: np.ndarray, direction: int, line: int, bc: int) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _, ny, nx = U.shape
+    n = nx if direction == DIR_X else ny
+    w = np.zeros((4, n + 4))
+    _load().oracle_load_pencil(_dptr(U), nx, ny, direction, line, bc, _dptr(w))
+    return w
+
+
+def _grid(U: np.ndarray) -> np.ndarray:
+    if U.dtype != np.float64 or not U.flags.c_contiguous or U.ndim != 3 or U.shape[0] != 4:
+        raise ValueError("oracle grids are contiguous float64 arrays [4, ny, nx]")
+    return U
+
+
+def sweep(U: np.ndarray, direction: int, dt: float, c: Cfg,
+          hist: np.ndarray | None = None) -> None:
+    """In-place directional sweep of U [4, ny, nx]."""
+    _grid(U)
+    _, ny, nx = U.shape
+    hp = hist.ctypes.data_as(_LL) if hist is not None else None
+    _load().oracle_sweep(_dptr(U), nx, ny, direction, dt, ctypes.byref(c), hp)
+
+
+def max_speed(U: np.ndarray, gamma=1.4) -> float:
+    _grid(U)
+    _, ny, nx = U.shape
+    return _load().oracle_max_speed(_dptr(U), nx, ny, gamma)
+
+
+def compute_dt(U: np.ndarray, c: Cfg) -> float:
+    _grid(U)
+    _, ny, nx = U.shape
+    return _load().oracle_compute_dt(_dptr(U), nx, ny, ctypes.byref(c))
+
+
+def step(U: np.ndarray, c: Cfg, hist: np.ndarray | None = None) -> float:
+    """In-place time step (dt, x-sweep, y-sweep); returns dt."""
+    _grid(U)
+    _, ny, nx = U.shape
+    hp = hist.ctypes.data_as(_LL) if hist is not None else None
+    return _load().oracle_step(_dptr(U), nx, ny, ctypes.byref(c), hp)
+
+
+def totals(U: np.ndarray) -> np.ndarray:
+    _grid(U)
+    _, ny, nx = U.shape
+    out = np.zeros(4)
+    _load().oracle_totals(_dptr(U), nx, ny, _dptr(out))
+    return out
+
+
+def threads() -> int:
+    return _load().oracle_threads()

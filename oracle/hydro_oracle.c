@@ -1,0 +1,410 @@
+/*
+ * hydro_oracle.c -- plain FP64 CPU oracle of the split second-order Godunov
+ * sweep.  TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU-baseline leg).
+ *
+ * Built with gcc -O2 -ffp-contract=off: every operation below rounds once,
+ * in the order written.  Nothing here is blocked, fused or reordered; each
+ * function is one step of the method as the paper orders it (Figure 5:
+ * primitive variables, Riemann problems at the interfaces, incoming fluxes,
+ * update), with the numerical readings the paper leaves open stated where
+ * they are taken.
+ */
+#include "hydro_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Primitive variables (Figure 5, COMPUTE: "compute primitive variables").    */
+/* Ideal-gas equation of state p = (gamma-1) (E - rho |u|^2 / 2).             */
+/* Reading: density floored at RHO_MIN, pressure at rho c_min^2 / gamma so    */
+/* that the sound speed never drops below C_MIN.                              */
+/* ------------------------------------------------------------------------ */
+double oracle_p_floor(double rho, double gamma) {
+  return rho * (ORACLE_C_MIN * ORACLE_C_MIN) / gamma;
+}
+
+void oracle_cons_to_prim(const double u[4], double gamma, double q[4]) {
+  double rho = fmax(u[0], ORACLE_RHO_MIN);
+  double un = u[1] / rho;
+  double ut = u[2] / rho;
+  double ekin = 0.5 * rho * (un * un + ut * ut);
+  double p = (gamma - 1.0) * (u[3] - ekin);
+  q[0] = rho;
+  q[1] = un;
+  q[2] = ut;
+  q[3] = fmax(p, oracle_p_floor(rho, gamma));
+}
+
+double oracle_sound_speed(const double q[4], double gamma) {
+  return sqrt(gamma * q[3] / q[0]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second-order reconstruction (Section 1: second-order Godunov scheme).      */
+/* Reading: minmod-limited slopes of the primitive variables.                 */
+/* ------------------------------------------------------------------------ */
+double oracle_minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  if (a > 0.0) return fmin(a, b);
+  return fmax(a, b);
+}
+
+/* MUSCL-Hancock half-step trace (reading; no characteristic projection).
+ * The primitive 1D Euler system q_t + A(q) q_x = 0 advanced by half a step
+ * with the limited slope as q_x gives the source S = -A(q) dq:
+ *   S_rho = -(u drho + rho du)
+ *   S_u   = -(u du + dp / rho)
+ *   S_ut  = -(u dut)
+ *   S_p   = -(u dp + gamma p du)
+ * and the face states q -/+ dq/2 + (dt/h) S / 2, floored. */
+void oracle_trace(const double q[4], const double dq[4], double gamma,
+                  double lam, double qm[4], double qp[4]) {
+  double rho = q[0], un = q[1], p = q[3];
+  double S[4];
+  S[0] = -(un * dq[0] + rho * dq[1]);
+  S[1] = -(un * dq[1] + dq[3] / rho);
+  S[2] = -(un * dq[2]);
+  S[3] = -(un * dq[3] + gamma * p * dq[1]);
+  for (int k = 0; k < 4; k++) {
+    double half_step = 0.5 * lam * S[k];
+    qm[k] = q[k] - 0.5 * dq[k] + half_step;
+    qp[k] = q[k] + 0.5 * dq[k] + half_step;
+  }
+  qm[0] = fmax(qm[0], ORACLE_RHO_MIN);
+  qp[0] = fmax(qp[0], ORACLE_RHO_MIN);
+  qm[3] = fmax(qm[3], oracle_p_floor(qm[0], gamma));
+  qp[3] = fmax(qp[3], oracle_p_floor(qp[0], gamma));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Riemann solver at a cell interface (Section 1, ref. [4]; Figure 5).        */
+/* ------------------------------------------------------------------------ */
+
+/* Smallest admissible star pressure for the pair (reading). */
+static double pmin_of(const double qL[4], const double qR[4], double gamma) {
+  return fmin(oracle_p_floor(qL[0], gamma), oracle_p_floor(qR[0], gamma));
+}
+
+/* Two-rarefaction guess: the star pressure when both waves are
+ * rarefactions, p = [(cL + cR - (gamma-1)(uR-uL)/2) /
+ *                    (cL pL^-z + cR pR^-z)]^(1/z),  z = (gamma-1)/(2 gamma);
+ * a non-positive numerator means vacuum forms, and the guess is the floor. */
+double oracle_ptr_guess(const double qL[4], const double qR[4], double gamma) {
+  double z = (gamma - 1.0) / (2.0 * gamma);
+  double cL = oracle_sound_speed(qL, gamma);
+  double cR = oracle_sound_speed(qR, gamma);
+  double pmin = pmin_of(qL, qR, gamma);
+  double num = cL + cR - 0.5 * (gamma - 1.0) * (qR[1] - qL[1]);
+  double p;
+  if (num <= 0.0) {
+    p = pmin;
+  } else {
+    double den = cL * pow(qL[3], -z) + cR * pow(qR[3], -z);
+    p = pow(num / den, 1.0 / z);
+  }
+  return fmax(p, pmin);
+}
+
+/* Lagrangian wave speed of side K at pressure p under the two-shock
+ * approximation: W_K^2 = C_K (1 + (gamma+1)/(2 gamma) (p - p_K)/p_K),
+ * C_K = gamma p_K rho_K. */
+static double shock_W(const double q[4], double gamma, double p) {
+  double C = gamma * q[3] * q[0];
+  double g = (gamma + 1.0) / (2.0 * gamma);
+  return sqrt(C * (1.0 + g * (p - q[3]) / q[3]));
+}
+
+double oracle_two_shock_f(const double qL[4], const double qR[4], double gamma,
+                          double p) {
+  double WL = shock_W(qL, gamma, p);
+  double WR = shock_W(qR, gamma, p);
+  return (p - qL[3]) / WL + (p - qR[3]) / WR + (qR[1] - qL[1]);
+}
+
+int oracle_riemann(const double qL[4], const double qR[4], double gamma,
+                   int niter, double tol, double qg[4], double *pstar_out,
+                   double *ustar_out, int *converged) {
+  double CL = gamma * qL[3] * qL[0];
+  double CR = gamma * qR[3] * qR[0];
+  double pmin = pmin_of(qL, qR, gamma);
+
+  /* star pressure: Newton on f from the two-rarefaction guess.  With
+   * z_K = 2 W_K^3 / (W_K^2 + C_K), f'(p) = 1/z_L + 1/z_R and
+   * -f(p) = u*_L - u*_R, so the Newton step is
+   * dp = z_L z_R / (z_L + z_R) (u*_L - u*_R). */
+  double p = oracle_ptr_guess(qL, qR, gamma);
+  int k = 0, conv = 0;
+  while (k < niter) {
+    k++;
+    double WL = shock_W(qL, gamma, p);
+    double WR = shock_W(qR, gamma, p);
+    double zL = 2.0 * WL * WL * WL / (WL * WL + CL);
+    double zR = 2.0 * WR * WR * WR / (WR * WR + CR);
+    double usL = qL[1] - (p - qL[3]) / WL;
+    double usR = qR[1] + (p - qR[3]) / WR;
+    double dp = zL * zR / (zL + zR) * (usL - usR);
+    p = fmax(p + dp, pmin);
+    if (fabs(dp) <= tol * p) {
+      conv = 1;
+      break;
+    }
+  }
+
+  /* star velocity at the final pressure (reading: the plain average of the
+   * two sides' estimates) */
+  double WL = shock_W(qL, gamma, p);
+  double WR = shock_W(qR, gamma, p);
+  double usL = qL[1] - (p - qL[3]) / WL;
+  double usR = qR[1] + (p - qR[3]) / WR;
+  double us = 0.5 * (usL + usR);
+
+  /* upwind side of the contact (reading: u* = 0 goes to the left side) */
+  const double *qo;
+  double Wo, s;
+  if (us >= 0.0) {
+    qo = qL;
+    Wo = WL;
+    s = 1.0;
+  } else {
+    qo = qR;
+    Wo = WR;
+    s = -1.0;
+  }
+  double ro = qo[0], uo = qo[1], po = qo[3];
+  double co = oracle_sound_speed(qo, gamma);
+
+  /* star density on that side, from the Lagrangian jump
+   * 1/rho* = 1/rho_o - (p* - p_o)/W_o^2 */
+  double rs = ro / (1.0 + ro * (po - p) / (Wo * Wo));
+  rs = fmax(rs, ORACLE_RHO_MIN);
+  double cs = fmax(ORACLE_C_MIN, sqrt(gamma * p / rs));
+
+  /* speeds of the outer and inner edge of the wave on that side, counted
+   * positive when they move away from the interface */
+  double sout, sin_;
+  if (p >= po) { /* shock: both edges move with it */
+    sout = Wo / ro - s * uo;
+    sin_ = sout;
+  } else { /* rarefaction: head and tail */
+    sout = co - s * uo;
+    sin_ = cs - s * us;
+  }
+
+  /* state at x/t = 0 (reading: linear interpolation across a fan) */
+  if (sout < 0.0) {
+    qg[0] = ro;
+    qg[1] = uo;
+    qg[3] = po;
+  } else if (sin_ > 0.0) {
+    qg[0] = rs;
+    qg[1] = us;
+    qg[3] = p;
+  } else {
+    double f = sout / fmax(sout - sin_, ORACLE_C_MIN);
+    f = fmin(fmax(f, 0.0), 1.0);
+    qg[0] = f * rs + (1.0 - f) * ro;
+    qg[1] = f * us + (1.0 - f) * uo;
+    qg[3] = f * p + (1.0 - f) * po;
+  }
+  qg[2] = qo[2]; /* transverse velocity is carried by the contact */
+
+  if (pstar_out) *pstar_out = p;
+  if (ustar_out) *ustar_out = us;
+  if (converged) *converged = conv;
+  return k;
+}
+
+/* Euler flux through an interface normal to the sweep direction
+ * (Figure 5: "compute incoming fluxes"). */
+void oracle_flux(const double qg[4], double gamma, double F[4]) {
+  double rho = qg[0], un = qg[1], ut = qg[2], p = qg[3];
+  double mass = rho * un;
+  F[0] = mass;
+  F[1] = mass * un + p;
+  F[2] = mass * ut;
+  F[3] = un * (gamma * p / (gamma - 1.0) + 0.5 * rho * (un * un + ut * ut));
+}
+
+/* ------------------------------------------------------------------------ */
+/* One pencil (Figure 5: READ into a 1D buffer, COMPUTE, WRITE back).          */
+/* ------------------------------------------------------------------------ */
+void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
+                   long long *hist) {
+  const double g = c->gamma;
+  const int m = n + 4; /* cells -2 .. n+1 */
+  double *q = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+  double *qm = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+  double *qp = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+  double *F = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+
+  /* primitive variables of cells -2 .. n+1 */
+  for (int j = 0; j < m; j++) {
+    double u[4] = {w[0 * m + j], w[1 * m + j], w[2 * m + j], w[3 * m + j]};
+    oracle_cons_to_prim(u, g, &q[4 * j]);
+  }
+  /* slopes and face states of cells -1 .. n */
+  for (int j = 1; j < m - 1; j++) {
+    double dq[4];
+    for (int k = 0; k < 4; k++)
+      dq[k] = oracle_minmod(q[4 * j + k] - q[4 * (j - 1) + k],
+                            q[4 * (j + 1) + k] - q[4 * j + k]);
+    oracle_trace(&q[4 * j], dq, g, lam, &qm[4 * j], &qp[4 * j]);
+  }
+  /* Riemann problem and flux at interfaces -1/2 .. n-1/2: interface between
+   * pencil columns j and j+1 is stored at F[j] */
+  for (int j = 1; j < m - 2; j++) {
+    double qg[4];
+    int conv;
+    int it = oracle_riemann(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter, c->tol,
+                            qg, NULL, NULL, &conv);
+    if (hist) hist[conv ? it : 0]++;
+    oracle_flux(qg, g, &F[4 * j]);
+  }
+  /* conservative update of cells 0 .. n-1 (columns 2 .. n+1) */
+  for (int j = 2; j < m - 2; j++)
+    for (int k = 0; k < 4; k++)
+      w[k * m + j] = w[k * m + j] + lam * (F[4 * (j - 1) + k] - F[4 * j + k]);
+
+  free(q);
+  free(qm);
+  free(qp);
+  free(F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary conditions (Figure 5: "apply boundary conditions").  Reading:     */
+/* two ghost cells per side (the stencil of Figures 1-2), filled before each  */
+/* sweep along that sweep's direction from the current state:                 */
+/*   periodic   ghost -g = cell n-g,  ghost n-1+g = cell g-1                  */
+/*   reflective ghost -g = cell g-1,  ghost n-1+g = cell n-g, normal momentum */
+/*              negated                                                        */
+/*   outflow    ghost -g = cell 0,    ghost n-1+g = cell n-1                  */
+/* ------------------------------------------------------------------------ */
+static long cell_index(int nx, int dir, int line, int i) {
+  /* offset of pencil cell i in one variable plane */
+  return dir == ORACLE_DIR_X ? (long)line * nx + i : (long)i * nx + line;
+}
+
+void oracle_load_pencil(const double *U, int nx, int ny, int dir, int line,
+                        int bc, double *w) {
+  const int n = dir == ORACLE_DIR_X ? nx : ny;
+  const int m = n + 4;
+  const long plane = (long)nx * ny;
+  /* conserved variable order in the pencil: rho, normal, transverse, E */
+  const int vmap[4] = {0, dir == ORACLE_DIR_X ? 1 : 2,
+                       dir == ORACLE_DIR_X ? 2 : 1, 3};
+  for (int j = 0; j < m; j++) {
+    int i = j - 2;
+    double sign = 1.0;
+    if (i < 0 || i >= n) {
+      int g = i < 0 ? -i : i - (n - 1); /* 1 or 2 */
+      if (bc == ORACLE_BC_PERIODIC) {
+        i = i < 0 ? n - g : g - 1;
+      } else if (bc == ORACLE_BC_REFLECT) {
+        i = i < 0 ? g - 1 : n - g;
+        sign = -1.0;
+      } else {
+        i = i < 0 ? 0 : n - 1;
+      }
+    }
+    long off = cell_index(nx, dir, line, i);
+    for (int k = 0; k < 4; k++) {
+      double v = U[vmap[k] * plane + off];
+      w[k * m + j] = k == 1 ? sign * v : v;
+    }
+  }
+}
+
+void oracle_sweep(double *U, int nx, int ny, int dir, double dt,
+                  const oracle_cfg *c, long long *hist) {
+  const int n = dir == ORACLE_DIR_X ? nx : ny;
+  const int lines = dir == ORACLE_DIR_X ? ny : nx;
+  const int m = n + 4;
+  const long plane = (long)nx * ny;
+  const double h = 1.0 / (double)(nx > ny ? nx : ny);
+  const double lam = dt / h;
+  const int vmap[4] = {0, dir == ORACLE_DIR_X ? 1 : 2,
+                       dir == ORACLE_DIR_X ? 2 : 1, 3};
+
+  /* Pencils are independent (Section 1), so they may run in any order;
+   * the result does not depend on the thread count. */
+#pragma omp parallel for schedule(static) if (hist == NULL)
+  for (int line = 0; line < lines; line++) {
+    double *w = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+    oracle_load_pencil(U, nx, ny, dir, line, c->bc, w);
+    oracle_pencil(w, n, lam, c, hist);
+    for (int i = 0; i < n; i++) {
+      long off = cell_index(nx, dir, line, i);
+      for (int k = 0; k < 4; k++) U[vmap[k] * plane + off] = w[k * m + i + 2];
+    }
+    free(w);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step (Figure 5: "for each time step n").  Reading: the CFL condition  */
+/* for split sweeps, dt = cfl h / max_cells max(|u|+c, |v|+c), from U^n,       */
+/* one dt for both sweeps.                                                     */
+/* ------------------------------------------------------------------------ */
+double oracle_max_speed(const double *U, int nx, int ny, double gamma) {
+  const long plane = (long)nx * ny;
+  double smax = 0.0;
+  for (long off = 0; off < plane; off++) {
+    double u[4] = {U[off], U[plane + off], U[2 * plane + off],
+                   U[3 * plane + off]};
+    double q[4];
+    oracle_cons_to_prim(u, gamma, q);
+    double c = oracle_sound_speed(q, gamma);
+    double s = fmax(fabs(q[1]) + c, fabs(q[2]) + c);
+    smax = fmax(smax, s);
+  }
+  return smax;
+}
+
+double oracle_compute_dt(const double *U, int nx, int ny, const oracle_cfg *c) {
+  const double h = 1.0 / (double)(nx > ny ? nx : ny);
+  return c->cfl * h / oracle_max_speed(U, nx, ny, c->gamma);
+}
+
+double oracle_step(double *U, int nx, int ny, const oracle_cfg *c,
+                   long long *hist) {
+  double dt = oracle_compute_dt(U, nx, ny, c);
+  oracle_sweep(U, nx, ny, ORACLE_DIR_X, dt, c, hist);
+  oracle_sweep(U, nx, ny, ORACLE_DIR_Y, dt, c, hist);
+  return dt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conserved totals: sum of U_k h^2 over interior cells, Neumaier-compensated */
+/* so that the oracle's own rounding stays a few ulp.                          */
+/* ------------------------------------------------------------------------ */
+void oracle_totals(const double *U, int nx, int ny, double out[4]) {
+  const long plane = (long)nx * ny;
+  const double h = 1.0 / (double)(nx > ny ? nx : ny);
+  for (int k = 0; k < 4; k++) {
+    double sum = 0.0, comp = 0.0;
+    for (long off = 0; off < plane; off++) {
+      double x = U[k * plane + off];
+      double t = sum + x;
+      if (fabs(sum) >= fabs(x))
+        comp += (sum - t) + x;
+      else
+        comp += (x - t) + sum;
+      sum = t;
+    }
+    out[k] = (sum + comp) * (h * h);
+  }
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
