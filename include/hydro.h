@@ -1,0 +1,150 @@
+/*
+ * hydro.h -- C ABI of the MI355X library for the directionally split,
+ * second-order Godunov sweep of the 2D compressible Euler equations.
+ *
+ * The problem is the one the paper states (Section 1): a fixed rectangular 2D
+ * domain, the compressible Euler equations of an ideal gas, a finite-volume
+ * discretisation, and a second-order Godunov scheme with directional
+ * splitting -- one 1D update per direction, performed successively, each
+ * solving a Riemann problem at every cell interface and updating the cells
+ * from the interface fluxes.  A 1D update of cell i reads cells i-2..i+2 of
+ * its pencil only (Figures 1 and 2); per pencil the work is READ, COMPUTE
+ * (primitive variables, Riemann problems, incoming fluxes), WRITE
+ * (Figure 5), with boundary conditions applied in every time step.
+ *
+ * Numerical readings (the paper delegates the details to its references):
+ * minmod-limited slopes of (rho, u_n, u_t, p); MUSCL-Hancock half-step trace;
+ * star pressure by Newton on the two-shock wave function from the
+ * two-rarefaction guess, stopped at |dp| <= tol*p or after niter iterations;
+ * linear sampling across rarefaction fans; CFL time step
+ * dt = cfl * h / max(|u|+c, |v|+c); floors rho >= 1e-10, c >= 1e-10.
+ *
+ * STATE LAYOUT.  U is a caller-owned device array [4][ny][pitch] of float64
+ * (HYDRO_F64) or float32 (HYDRO_F32): planes rho, rho*u, rho*v, E; x is the
+ * fastest index, pitch >= nx elements (a multiple of 64 keeps rows aligned).
+ * Interior cells only: ghost cells never live in user memory.  Cells are
+ * square, h = 1 / max(nx, ny).  The library never frees caller memory.
+ * Sweeps are out of place: the handle owns a second buffer of the same size
+ * (allocated by hydro_bind), an x-sweep writes it and the y-sweep writes U
+ * back, so after every call U holds the current state.
+ *
+ * ERRORS.  Every call returns HYDRO_OK (0) or a negative code and sets a
+ * thread-local message (hydro_last_error).  No call aborts or throws.
+ * HIP failures map to HYDRO_EDEVICE.  Non-physical states met by a sweep
+ * (non-finite values, rho <= 0) are latched on the device and reported as
+ * HYDRO_ENONPHYS by the next call that synchronises.
+ *
+ * STREAMS.  All device work of a handle runs on the stream given to
+ * hydro_bind, in order.  hydro_sweep and hydro_step never synchronise and
+ * keep dt on the device, so they can be captured into a HIP graph;
+ * hydro_compute_dt, hydro_conserved_totals, hydro_get_clock and
+ * hydro_riemann_stats synchronise that stream.  A handle is not thread-safe;
+ * separate handles are independent.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hydro_s hydro_t;
+
+enum { HYDRO_BC_REFLECT = 1, HYDRO_BC_OUTFLOW = 2, HYDRO_BC_PERIODIC = 3 };
+enum { HYDRO_DIR_X = 0, HYDRO_DIR_Y = 1 };
+enum { HYDRO_F64 = 0, HYDRO_F32 = 1 };
+enum { HYDRO_GUESS_PTR = 0, HYDRO_GUESS_MLP = 1 };
+enum {
+  HYDRO_OK = 0,
+  HYDRO_EINVAL = -1,   /* bad argument                                   */
+  HYDRO_ENOMEM = -2,   /* device allocation failed                       */
+  HYDRO_EDEVICE = -3,  /* HIP runtime error                              */
+  HYDRO_ENONPHYS = -4, /* a sweep produced a non-physical state          */
+  HYDRO_ESTATE = -5    /* call not valid in the handle's state (unbound) */
+};
+
+#define HYDRO_MAX_NITER 32
+
+/* Solver options (hydro_set_options).  Defaults: niter 10, tol 1e-8,
+ * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library. */
+typedef struct {
+  int niter;     /* Newton iteration cap, 1..HYDRO_MAX_NITER              */
+  double tol;    /* convergence test |dp| <= tol * p, > 0                  */
+  int guess;     /* HYDRO_GUESS_PTR or HYDRO_GUESS_MLP (needs hydro_set_mlp)*/
+  int stats;     /* nonzero: count Newton iterations per interface         */
+  int seg_x;     /* x-sweep: consecutive 60-cell wave segments per wave;
+                    0 = library default                                    */
+  int seg_y;     /* y-sweep: cells per marching thread; 0 = default        */
+} hydro_options_t;
+
+/* Riemann-solver statistics accumulated since the last reset
+ * (hydro_riemann_stats).  Collected only while options.stats != 0. */
+typedef struct {
+  long long interfaces;                  /* Riemann problems solved         */
+  long long hist[HYDRO_MAX_NITER + 1];   /* hist[k]: converged after k
+                                            iterations; hist[0]: iteration
+                                            cap reached unconverged         */
+  long long fallbacks;                   /* learned guess rejected          */
+} hydro_stats_t;
+
+/* Create a solver for an nx x ny grid (both >= 2) of an ideal gas with ratio
+ * of specific heats gamma > 1, Courant number 0 < cfl <= 1 and boundary type
+ * bc (one of HYDRO_BC_*, applied on all four sides).  Allocates the handle's
+ * small device scratch on the current HIP device.  Returns NULL on error
+ * (hydro_last_error gives the reason). */
+hydro_t *hydro_create(int nx, int ny, double gamma, double cfl, int bc);
+
+/* Release the handle and its scratch (never the bound state). NULL is a no-op. */
+void hydro_destroy(hydro_t *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hydro_last_error(void);
+
+/* Bind the state U (device pointer, layout above, pitch in elements) of type
+ * dtype and the HIP stream (hipStream_t; NULL = default stream) all later
+ * work runs on.  Rebinding is allowed; it invalidates the fused max speed, so
+ * the next step recomputes dt from U.  Call it again (or hydro_invalidate)
+ * after modifying U outside the library. */
+int hydro_bind(hydro_t *h, void *U, long pitch, int dtype, void *hip_stream);
+
+/* Forget the max wave speed fused into the last y-sweep (U changed outside
+ * the library). */
+int hydro_invalidate(hydro_t *h);
+
+int hydro_set_options(hydro_t *h, const hydro_options_t *o);
+int hydro_get_options(const hydro_t *h, hydro_options_t *o);
+
+/* Time step from the bound state: dt = cfl * h / max over cells of
+ * max(|u|+c, |v|+c).  Stores dt on the device for later sweeps and returns
+ * it (> 0), or a negative error code.  Synchronises the stream. */
+double hydro_compute_dt(hydro_t *h);
+
+/* One directional sweep (HYDRO_DIR_X: rows, HYDRO_DIR_Y: columns) of the
+ * bound state with the stored dt, boundary conditions applied along that
+ * direction (two ghost cells per side).  Asynchronous.  Does not advance the
+ * clock. */
+int hydro_sweep(hydro_t *h, int dir);
+
+/* One time step: dt from the current state (taken from the max wave speed
+ * fused into the previous step's y-sweep when still valid, otherwise from a
+ * reduction over U), x-sweep, y-sweep; t += dt, step += 1 on the device.
+ * Asynchronous, no host synchronisation. */
+int hydro_step(hydro_t *h);
+
+/* out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E), summed in
+ * FP64 in a fixed order (deterministic), also for float32 states.
+ * Synchronises the stream. */
+int hydro_conserved_totals(hydro_t *h, double out[4]);
+
+/* Simulated time, steps taken and the last dt (device clock).  Synchronises. */
+int hydro_get_clock(hydro_t *h, double *t, long *step, double *dt);
+/* Set the device clock (checkpoint restart); dt is kept.  Asynchronous. */
+int hydro_set_clock(hydro_t *h, double t, long step);
+
+/* Copy the Riemann statistics (synchronises); reset clears them. */
+int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDRO_H */

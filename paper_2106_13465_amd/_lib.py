@@ -1,0 +1,100 @@
+"""ctypes binding of libhydro.so (include/hydro.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  There is no
+fallback: if the library is missing, loading raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhydro.so")
+
+HYDRO_BC_REFLECT, HYDRO_BC_OUTFLOW, HYDRO_BC_PERIODIC = 1, 2, 3
+HYDRO_DIR_X, HYDRO_DIR_Y = 0, 1
+HYDRO_F64, HYDRO_F32 = 0, 1
+HYDRO_GUESS_PTR, HYDRO_GUESS_MLP = 0, 1
+HYDRO_OK, HYDRO_EINVAL, HYDRO_ENOMEM, HYDRO_EDEVICE, HYDRO_ENONPHYS, HYDRO_ESTATE = 0, -1, -2, -3, -4, -5
+HYDRO_MAX_NITER = 32
+
+ERROR_NAMES = {
+    HYDRO_EINVAL: "HYDRO_EINVAL",
+    HYDRO_ENOMEM: "HYDRO_ENOMEM",
+    HYDRO_EDEVICE: "HYDRO_EDEVICE",
+    HYDRO_ENONPHYS: "HYDRO_ENONPHYS",
+    HYDRO_ESTATE: "HYDRO_ESTATE",
+}
+
+
+class hydro_options_t(ctypes.Structure):
+    _fields_ = [
+        ("niter", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("guess", ctypes.c_int),
+        ("stats", ctypes.c_int),
+        ("seg_x", ctypes.c_int),
+        ("seg_y", ctypes.c_int),
+    ]
+
+
+class hydro_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("interfaces", ctypes.c_longlong),
+        ("hist", ctypes.c_longlong * (HYDRO_MAX_NITER + 1)),
+        ("fallbacks", ctypes.c_longlong),
+    ]
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+SIGNATURES = {
+    "hydro_create": (_vp, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "hydro_destroy": (None, [_vp]),
+    "hydro_last_error": (ctypes.c_char_p, []),
+    "hydro_bind": (ctypes.c_int, [_vp, _vp, ctypes.c_long, ctypes.c_int, _vp]),
+    "hydro_invalidate": (ctypes.c_int, [_vp]),
+    "hydro_set_options": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_options_t)]),
+    "hydro_get_options": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_options_t)]),
+    "hydro_compute_dt": (ctypes.c_double, [_vp]),
+    "hydro_sweep": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "hydro_step": (ctypes.c_int, [_vp]),
+    "hydro_conserved_totals": (ctypes.c_int, [_vp, _D]),
+    "hydro_get_clock": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_long), _D]),
+    "hydro_set_clock": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long]),
+    "hydro_riemann_stats": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_stats_t), ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhydro.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2106_13465_amd.build` "
+            "(there is no non-HIP fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().hydro_last_error().decode()
+
+
+def check(rc) -> None:
+    if rc != HYDRO_OK:
+        raise HydroError(int(rc), last_error())

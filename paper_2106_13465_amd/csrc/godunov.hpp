@@ -1,0 +1,249 @@
+// godunov.hpp -- device numerics of one 1D second-order Godunov update:
+// primitive variables, minmod slopes, MUSCL-Hancock trace, two-shock Riemann
+// solver and interface flux (paper, Section 1 and Figure 5; the numerical
+// readings are stated in include/hydro.h).  Written for gfx950, templated on
+// the arithmetic type (double or float).  Division and square roots are
+// arranged to share reciprocals: per Newton iteration two reciprocal square
+// roots and one division.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hydro {
+
+constexpr double kRhoMin = 1e-10;
+constexpr double kCMin = 1e-10;
+
+// Gas constants, computed once on the host in double and cast to T.
+template <typename T>
+struct Gas {
+  T g;         // gamma
+  T gm1;       // gamma - 1
+  T gs;        // (gamma + 1) / (2 gamma): two-shock wave-speed factor
+  T z;         // (gamma - 1) / (2 gamma): two-rarefaction exponent
+  T inv_z;     // 1 / z
+  T half_gm1;  // (gamma - 1) / 2
+  T h_coef;    // gamma / (gamma - 1): enthalpy factor of the energy flux
+  T pfloor;    // c_min^2 / gamma: pressure floor per unit density
+  T rho_min;
+  T c_min;
+  T tol;       // Newton convergence test |dp| <= tol * p
+  int niter;   // Newton iteration cap
+};
+
+template <typename T>
+struct Prim {
+  T r, u, t, p;  // density, normal velocity, transverse velocity, pressure
+};
+
+template <typename T>
+__device__ __forceinline__ T rcp(T x) {
+  return T(1) / x;
+}
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_(T x);
+template <>
+__device__ __forceinline__ double rsqrt_<double>(double x) {
+  return rsqrt(x);
+}
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x) {
+  return rsqrtf(x);
+}
+
+template <typename T>
+__device__ __forceinline__ T pow_(T x, T y);
+template <>
+__device__ __forceinline__ double pow_<double>(double x, double y) {
+  return pow(x, y);
+}
+template <>
+__device__ __forceinline__ float pow_<float>(float x, float y) {
+  return powf(x, y);
+}
+
+// Conservative (rho, m_n, m_t, E) -> primitive, with floors; also returns
+// 1/rho for the trace.
+template <typename T>
+__device__ __forceinline__ Prim<T> cons_to_prim(T U0, T Un, T Ut, T E, const Gas<T>& G,
+                                                T& ir) {
+  Prim<T> q;
+  q.r = fmax(U0, G.rho_min);
+  ir = rcp(q.r);
+  q.u = Un * ir;
+  q.t = Ut * ir;
+  T ek = T(0.5) * q.r * (q.u * q.u + q.t * q.t);
+  q.p = fmax(G.gm1 * (E - ek), q.r * G.pfloor);
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  T m = a > T(0) ? fmin(a, b) : fmax(a, b);
+  return a * b <= T(0) ? T(0) : m;
+}
+
+// MUSCL-Hancock half-step trace of one cell: face states at x_{i-1/2} (qm)
+// and x_{i+1/2} (qp) from the cell state q, its limited slopes d and
+// lam = dt/h.  Source of the half step: S = -A(q) d.
+template <typename T>
+__device__ __forceinline__ void trace(const Prim<T>& q, T ir, const Prim<T>& d, T lam,
+                                      const Gas<T>& G, Prim<T>& qm, Prim<T>& qp) {
+  T hl = T(0.5) * lam;
+  T sr = -(q.u * d.r + q.r * d.u) * hl;
+  T su = -(q.u * d.u + d.p * ir) * hl;
+  T st = -(q.u * d.t) * hl;
+  T sp = -(q.u * d.p + G.g * q.p * d.u) * hl;
+  T hr = T(0.5) * d.r, hu = T(0.5) * d.u, ht = T(0.5) * d.t, hp = T(0.5) * d.p;
+  qm.r = fmax(q.r - hr + sr, G.rho_min);
+  qp.r = fmax(q.r + hr + sr, G.rho_min);
+  qm.u = q.u - hu + su;
+  qp.u = q.u + hu + su;
+  qm.t = q.t - ht + st;
+  qp.t = q.t + ht + st;
+  qm.p = fmax(q.p - hp + sp, qm.r * G.pfloor);
+  qp.p = fmax(q.p + hp + sp, qp.r * G.pfloor);
+}
+
+// Interface flux (mass, normal momentum, transverse momentum, energy).
+template <typename T>
+struct Flux {
+  T m, n, t, e;
+};
+
+// Riemann problem at one interface: left state L, right state R.  Returns the
+// flux of the Godunov state at x/t = 0; iters/converged report the Newton
+// solve.  p0 is an optional starting guess (<= 0: two-rarefaction guess).
+template <typename T>
+__device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
+                                                const Gas<T>& G, int& iters,
+                                                bool& converged) {
+  const T irL = rcp(L.r), irR = rcp(R.r);
+  const T cL = sqrt(G.g * L.p * irL);
+  const T cR = sqrt(G.g * R.p * irR);
+  const T CL = G.g * L.p * L.r;  // Lagrangian sound speed squared
+  const T CR = G.g * R.p * R.r;
+  const T ipL = rcp(L.p), ipR = rcp(R.p);
+  const T pmin = fmin(L.r, R.r) * G.pfloor;
+
+  // two-rarefaction guess
+  T p;
+  const T num = cL + cR - G.half_gm1 * (R.u - L.u);
+  if (num > T(0)) {
+    T den = cL * pow_(L.p, -G.z) + cR * pow_(R.p, -G.z);
+    p = pow_(num / den, G.inv_z);
+  } else {
+    p = pmin;
+  }
+  p = fmax(p, pmin);
+
+  // Newton on f(p) = sum_K (p - p_K)/W_K + u_R - u_L with the two-shock
+  // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
+  // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
+  int k = 0;
+  bool conv = false;
+  while (k < G.niter) {
+    ++k;
+    T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
+    T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+    T iWL = rsqrt_(XL), iWR = rsqrt_(XR);
+    T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
+    T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
+    T usL = L.u - (p - L.p) * iWL;
+    T usR = R.u + (p - R.p) * iWR;
+    T dp = (usL - usR) / (izL + izR);
+    p = fmax(p + dp, pmin);
+    if (fabs(dp) <= G.tol * p) {
+      conv = true;
+      break;
+    }
+  }
+  iters = k;
+  converged = conv;
+
+  // star velocity (average of the two sides' estimates) at the final p
+  T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
+  T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+  T iWL = rsqrt_(XL), iWR = rsqrt_(XR);
+  T usL = L.u - (p - L.p) * iWL;
+  T usR = R.u + (p - R.p) * iWR;
+  T us = T(0.5) * (usL + usR);
+
+  // upwind side of the contact (u* = 0 -> left)
+  const bool left = us >= T(0);
+  const T ro = left ? L.r : R.r;
+  const T uo = left ? L.u : R.u;
+  const T to = left ? L.t : R.t;
+  const T po = left ? L.p : R.p;
+  const T iro = left ? irL : irR;
+  const T co = left ? cL : cR;
+  const T Xo = left ? XL : XR;
+  const T iWo = left ? iWL : iWR;
+  const T s = left ? T(1) : T(-1);
+
+  // star density: 1/rho* = 1/rho_o - (p* - p_o)/W_o^2, floored
+  T irs = iro + (po - p) * (iWo * iWo);
+  irs = fmin(irs, rcp(G.rho_min));
+  const T rs = rcp(irs);
+  const T cs = fmax(G.c_min, sqrt(G.g * p * irs));
+
+  // outer/inner edge speeds of the wave on that side, positive away from
+  // the interface
+  T sout, sin_;
+  if (p >= po) {
+    sout = Xo * iWo * iro - s * uo;  // shock: W_o / rho_o - s u_o
+    sin_ = sout;
+  } else {
+    sout = co - s * uo;
+    sin_ = cs - s * us;
+  }
+
+  T gr, gu, gp;
+  if (sout < T(0)) {
+    gr = ro;
+    gu = uo;
+    gp = po;
+  } else if (sin_ > T(0)) {
+    gr = rs;
+    gu = us;
+    gp = p;
+  } else {
+    T f = sout / fmax(sout - sin_, G.c_min);
+    f = fmin(fmax(f, T(0)), T(1));
+    gr = f * rs + (T(1) - f) * ro;
+    gu = f * us + (T(1) - f) * uo;
+    gp = f * p + (T(1) - f) * po;
+  }
+
+  Flux<T> F;
+  F.m = gr * gu;
+  F.n = F.m * gu + gp;
+  F.t = F.m * to;
+  F.e = gu * (G.h_coef * gp + T(0.5) * gr * (gu * gu + to * to));
+  return F;
+}
+
+// Largest signal speed of a cell for the CFL condition: max(|u|+c, |v|+c).
+template <typename T>
+__device__ __forceinline__ T max_speed(T U0, T U1, T U2, T E, const Gas<T>& G) {
+  T ir;
+  Prim<T> q = cons_to_prim(U0, U1, U2, E, G, ir);
+  T c = sqrt(G.g * q.p * ir);
+  return fmax(fabs(q.u), fabs(q.t)) + c;
+}
+
+// Ghost-cell source index along a pencil of n cells for index i in [-2, n+1]
+// (boundary conditions, two ghost cells per side); flip = normal momentum
+// changes sign (reflective walls).
+__device__ __forceinline__ int ghost_source(int i, int n, int bc, bool& flip) {
+  flip = false;
+  if (i >= 0 && i < n) return i;
+  if (bc == 3) return i < 0 ? i + n : i - n;  // periodic
+  if (bc == 1) {                               // reflective
+    flip = true;
+    return i < 0 ? -1 - i : 2 * n - 1 - i;
+  }
+  return i < 0 ? 0 : n - 1;  // outflow
+}
+
+}  // namespace hydro
