@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the split second-order Godunov step on one MI355X.
+
+A step is one pass of the whole hot path over the grid: the CFL time step
+(max wave speed fused into the previous y-sweep), the x-sweep and the y-sweep
+(paper, Figure 5).  The default workload is the 8192 x 8192 periodic flow of 16
+seeded Fourier modes plus 8 point blasts, 200 steps; the state is resident in
+HBM before timing starts.
+
+Prints one JSON line: whole-step cell-updates/s (two cell-updates per cell per
+step), per-sweep times from HIP events recorded on the library's stream, the
+roofline of the dominant sweep kernel, the FP32 variant, and the FP64 CPU
+oracle timed on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per split step & HBM GB/s vs peak; learned+FP32 vs plain FP64"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_fourier_blasts_8192_pmc.json")
+KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/godunov.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, n: int):
+    from paper_2106_13465_amd import inputs
+
+    if name == "fourier_blasts":
+        return inputs.fourier_blasts(n), "periodic", (
+            f"fourier_blasts {n}x{n}: rho = 1 + 0.3 S, u, v in [-0.5, 0.5] from 16 seeded "
+            "Fourier modes (k <= 8), p = 1, 8 seeded point blasts E = 1/h^2; periodic")
+    if name == "shear_layer":
+        return inputs.shear_layer(n), "periodic", (
+            f"shear_layer {n}x{n}: Kelvin-Helmholtz layer rho 2/1, u +-0.5, p 2.5, "
+            "seeded v noise 0.01; periodic")
+    if name == "blast_corner":
+        return inputs.blast_corner(n), "reflect", (
+            f"blast_corner {n}x{n}: rho 1, p 1e-5, corner cell E = 1/h^2; reflective")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0):
+    import torch
+
+    from paper_2106_13465_amd.hydro import Hydro
+
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    _, ny, nx = U.shape
+    h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0")
+    if seg_x or seg_y:
+        h.set_options(seg_x=seg_x, seg_y=seg_y)
+    h.set_state(U)
+    h.step(warmup)
+    torch.cuda.synchronize()
+    h.profile(reset=True)
+    h.set_profiling(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(h.stream)
+    t0 = time.perf_counter()
+    h.step(steps)
+    stop.record(h.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    prof = h.profile(reset=True)
+    h.set_profiling(False)
+    t, nsteps, dt = h.clock()
+    return h, {"ms_total": ms_total, "wall_s": wall, "profile": prof, "t": t, "steps_done": nsteps,
+               "dt": dt}
+
+
+def sweep_record(cells, elem, phase):
+    ms = phase["ms"] / max(phase["launches"], 1)
+    alg_bytes = cells * 8 * elem  # read 4 words + write 4 words per cell
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"avg_ms": ms, "launches": phase["launches"], "cell_updates_per_s": cells / (ms * 1e-3),
+            "algorithmic_bytes": alg_bytes, "hbm_gbps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
+def pmc_traffic(kernel: str, dtype_name: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if missing or taken from different kernel sources."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}_{dtype_name}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(U, bc_name):
+    import oracle
+
+    bc = {"periodic": oracle.BC_PERIODIC, "reflect": oracle.BC_REFLECT,
+          "outflow": oracle.BC_OUTFLOW}[bc_name]
+    c = oracle.cfg(bc=bc)
+    V = U.copy()
+    _, ny, nx = V.shape
+    t0 = time.perf_counter()
+    oracle.step(V, c)
+    sec = time.perf_counter() - t0
+    return {"value": 2.0 * nx * ny / sec, "unit": "cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle", "seconds": sec,
+            "sample": f"1 full step (dt, x-sweep, y-sweep) of the same {nx}x{ny} input, FP64, "
+                      f"{oracle.threads()} OpenMP threads over pencils"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--workload", default="fourier_blasts",
+                    choices=["fourier_blasts", "shear_layer", "blast_corner"])
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seg-x", type=int, default=0)
+    ap.add_argument("--seg-y", type=int, default=0)
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="also run a plain device copy of the state (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the sweep runs on a single MI355X in this build "
+              "(multi-GPU slab decomposition is not implemented); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    print(f"# generating {args.workload} {args.size}^2", file=sys.stderr, flush=True)
+    U, bc, desc = workload(args.workload, args.size)
+    _, ny, nx = U.shape
+    cells = nx * ny
+
+    variants = [args.dtype] + ([] if args.no_f32 or args.dtype == "f32" else ["f32"])
+    results = {}
+    states = {}
+    for dn in variants:
+        print(f"# gpu {dn}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+              flush=True)
+        h, r = run_gpu(U, bc, dn, args.steps, args.warmup, args.seg_x, args.seg_y)
+        elem = 8 if dn == "f64" else 4
+        ms_step = r["ms_total"] / args.steps
+        sx = sweep_record(cells, elem, r["profile"]["sweep_x"])
+        sy = sweep_record(cells, elem, r["profile"]["sweep_y"])
+        results[dn] = {
+            "value": 2.0 * cells * args.steps / (r["ms_total"] * 1e-3),
+            "ms_per_step": ms_step,
+            "sweeps": {"x": sx, "y": sy},
+            "dt_phase_avg_ms": r["profile"]["dt"]["ms"] / max(r["profile"]["dt"]["launches"], 1),
+            "sim_time": r["t"],
+        }
+        states[dn] = h.get_state()
+        if args.copy_calibrate:
+            src = h.U.clone()
+            torch.cuda.synchronize()
+            for _ in range(3):
+                h.U.copy_(src)
+            torch.cuda.synchronize()
+            del src
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+
+    main_dn = variants[0]
+    res = results[main_dn]
+    sx, sy = res["sweeps"]["x"], res["sweeps"]["y"]
+    dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
+    traffic = pmc_traffic(dom_name, main_dn)
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
+                "traffic": traffic, "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
+                "avg_launch_ms": dom["avg_ms"]}
+
+    line = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_dn,
+        "data": "synthetic",
+        "config": {"workload": desc, "nx": nx, "ny": ny, "bc": bc, "gamma": 1.4, "cfl": 0.8,
+                   "limiter": "minmod", "newton_cap": 10, "newton_tol": 1e-8,
+                   "parallelism": "single GPU"},
+        "sweeps": res["sweeps"],
+        "roofline": roofline,
+    }
+    if "f32" in results and main_dn != "f32":
+        r32 = results["f32"]
+        a, b = states["f32"].astype(np.float64), states[main_dn]
+        l1 = [float(np.abs(a[k] - b[k]).sum() / max(np.abs(b[k]).sum(), 1e-300)) for k in range(4)]
+        line["f32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                       "sweeps": r32["sweeps"],
+                       "speedup_vs_f64": r32["value"] / res["value"],
+                       "rel_l1_vs_f64_after_steps": l1}
+    del states
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(U, bc)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -144,6 +144,16 @@ int hydro_set_clock(hydro_t *h, double t, long step);
 /* Copy the Riemann statistics (synchronises); reset clears them. */
 int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
 
+/* Kernel timing.  While enabled, hydro_step records a HIP event pair on the
+ * bound stream around each of its phases (dt, x-sweep, y-sweep), except
+ * under stream capture.  hydro_get_profile synchronises, returns the summed
+ * durations in milliseconds and launch counts per phase since the last
+ * reset, and optionally resets them. */
+enum { HYDRO_PHASE_DT = 0, HYDRO_PHASE_SWEEP_X = 1, HYDRO_PHASE_SWEEP_Y = 2, HYDRO_NPHASES = 3 };
+int hydro_set_profiling(hydro_t *h, int enable);
+int hydro_get_profile(hydro_t *h, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
+                      int reset);
+
 #ifdef __cplusplus
 }
 #endif

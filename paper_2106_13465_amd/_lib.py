@@ -15,6 +15,8 @@ HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_GUESS_PTR, HYDRO_GUESS_MLP = 0, 1
 HYDRO_OK, HYDRO_EINVAL, HYDRO_ENOMEM, HYDRO_EDEVICE, HYDRO_ENONPHYS, HYDRO_ESTATE = 0, -1, -2, -3, -4, -5
 HYDRO_MAX_NITER = 32
+HYDRO_PHASE_DT, HYDRO_PHASE_SWEEP_X, HYDRO_PHASE_SWEEP_Y, HYDRO_NPHASES = 0, 1, 2, 3
+PHASE_NAMES = ("dt", "sweep_x", "sweep_y")
 
 ERROR_NAMES = {
     HYDRO_EINVAL: "HYDRO_EINVAL",
@@ -68,6 +70,8 @@ SIGNATURES = {
     "hydro_get_clock": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_long), _D]),
     "hydro_set_clock": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long]),
     "hydro_riemann_stats": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_stats_t), ctypes.c_int]),
+    "hydro_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "hydro_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
 }
 
 _lib = None

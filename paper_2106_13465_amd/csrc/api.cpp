@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "hydro.h"
 #include "launch.hpp"
@@ -31,6 +32,14 @@ struct hydro_s {
   hipStream_t stream;
   bool bound;
   bool acc_valid;     // st->acc holds the max speed of the current U
+  // kernel timing: event pairs recorded around the phases of hydro_step
+  bool profiling;
+  std::vector<hipEvent_t> ev_pool;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
 };
 
 namespace {
@@ -151,13 +160,41 @@ hipError_t enqueue_single_sweep(hydro_t* h, int dir) {
   return hydro::launch_copy<T>(grid_args<T>(h, h->V, h->U), h->stream);
 }
 
-// A full step's sweeps: x-sweep U -> V, y-sweep V -> U (max speed fused).
-template <typename T>
-hipError_t enqueue_step_sweeps(hydro_t* h) {
-  hipError_t e = enqueue_sweep<T>(h, HYDRO_DIR_X, false, h->U, h->V);
-  if (e != hipSuccess) return e;
-  return enqueue_sweep<T>(h, HYDRO_DIR_Y, true, h->V, h->U);
-}
+// Event pair around one phase of a step (no-op unless profiling and the
+// stream is not being captured).
+struct PhaseTimer {
+  hydro_t* h;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseTimer(hydro_t* h_, int phase_) : h(h_), phase(phase_) {
+    if (!h->profiling) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, h->stream);
+  }
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!h->ev_pool.empty()) {
+      e = h->ev_pool.back();
+      h->ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  ~PhaseTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, h->stream);
+      h->marks.push_back({phase, a, b});
+    } else {
+      if (a) h->ev_pool.push_back(a);
+      if (b) h->ev_pool.push_back(b);
+    }
+  }
+};
 
 int check_bound(const hydro_t* h) {
   if (!h) return fail(HYDRO_EINVAL, "NULL handle");
@@ -230,6 +267,7 @@ hydro_t* hydro_create(int nx, int ny, double gamma, double cfl, int bc) {
   h->bound = false;
   h->acc_valid = false;
   h->stream = nullptr;
+  h->profiling = false;
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipMalloc((void**)&h->st, sizeof(DevState));
   if (e == hipSuccess)
@@ -251,6 +289,11 @@ void hydro_destroy(hydro_t* h) {
   if (h->st) (void)hipFree(h->st);
   if (h->partials) (void)hipFree(h->partials);
   if (h->V) (void)hipFree(h->V);
+  for (auto& m : h->marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -357,9 +400,22 @@ int hydro_step(hydro_t* h) {
   DeviceGuard g(h->device);
   hipError_t e = hipSuccess;
   const bool f64 = h->dtype == HYDRO_F64;
-  if (!h->acc_valid) e = f64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
-  if (e == hipSuccess) e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, true, true, h->stream);
-  if (e == hipSuccess) e = f64 ? enqueue_step_sweeps<double>(h) : enqueue_step_sweeps<float>(h);
+  {
+    PhaseTimer pt(h, HYDRO_PHASE_DT);
+    if (!h->acc_valid) e = f64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
+    if (e == hipSuccess)
+      e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, true, true, h->stream);
+  }
+  if (e == hipSuccess) {
+    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_X);
+    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_X, false, h->U, h->V)
+            : enqueue_sweep<float>(h, HYDRO_DIR_X, false, h->U, h->V);
+  }
+  if (e == hipSuccess) {
+    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_Y);
+    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_Y, true, h->V, h->U)
+            : enqueue_sweep<float>(h, HYDRO_DIR_Y, true, h->V, h->U);
+  }
   if (e != hipSuccess) {
     h->acc_valid = false;
     return dev_fail(e, "hydro_step");
@@ -420,6 +476,43 @@ int hydro_riemann_stats(hydro_t* h, hydro_stats_t* out, int reset) {
   if (reset) {
     e = hydro::launch_clear_stats(h->st, h->stream);
     if (e != hipSuccess) return dev_fail(e, "stats reset");
+  }
+  return HYDRO_OK;
+}
+
+int hydro_set_profiling(hydro_t* h, int enable) {
+  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
+  h->profiling = enable != 0;
+  return HYDRO_OK;
+}
+
+int hydro_get_profile(hydro_t* h, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
+                      int reset) {
+  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
+  DeviceGuard g(h->device);
+  if (h->stream || h->bound) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_fail(e, "hydro_get_profile");
+  }
+  double acc[HYDRO_NPHASES] = {0, 0, 0};
+  long long cnt[HYDRO_NPHASES] = {0, 0, 0};
+  for (const auto& m : h->marks) {
+    float t = 0.f;
+    hipError_t e = hipEventElapsedTime(&t, m.a, m.b);
+    if (e != hipSuccess) return dev_fail(e, "hipEventElapsedTime");
+    acc[m.phase] += t;
+    cnt[m.phase] += 1;
+  }
+  for (int k = 0; k < HYDRO_NPHASES; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  if (reset) {
+    for (const auto& m : h->marks) {
+      h->ev_pool.push_back(m.a);
+      h->ev_pool.push_back(m.b);
+    }
+    h->marks.clear();
   }
   return HYDRO_OK;
 }

@@ -144,6 +144,16 @@ class Hydro:
     def invalidate(self) -> None:
         check(self.lib.hydro_invalidate(self.handle))
 
+    def set_profiling(self, enable: bool = True) -> None:
+        check(self.lib.hydro_set_profiling(self.handle, int(enable)))
+
+    def profile(self, reset: bool = True) -> dict:
+        """Summed kernel time (ms) and launch count per step phase."""
+        ms = (ctypes.c_double * _lib.HYDRO_NPHASES)()
+        n = (ctypes.c_longlong * _lib.HYDRO_NPHASES)()
+        check(self.lib.hydro_get_profile(self.handle, ms, n, int(reset)))
+        return {name: {"ms": ms[k], "launches": n[k]} for k, name in enumerate(_lib.PHASE_NAMES)}
+
     def stats(self, reset: bool = False) -> dict:
         s = _lib.hydro_stats_t()
         check(self.lib.hydro_riemann_stats(self.handle, ctypes.byref(s), int(reset)))
