@@ -87,6 +87,20 @@ def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0):
                "dt": dt}
 
 
+def newton_report(h):
+    """Newton iterations per interface over one extra (untimed) step."""
+    h.set_options(stats=1)
+    h.stats(reset=True)
+    h.step(1)
+    s = h.stats(reset=True)
+    h.set_options(stats=0)
+    hist = s["hist"]
+    conv = sum(hist[1:])
+    mean = sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1)
+    return {"interfaces": s["interfaces"], "mean_iterations": mean, "unconverged": hist[0],
+            "hist": {str(k): n for k, n in enumerate(hist) if n}}
+
+
 def sweep_record(cells, elem, phase):
     ms = phase["ms"] / max(phase["launches"], 1)
     alg_bytes = cells * 8 * elem  # read 4 words + write 4 words per cell
@@ -177,6 +191,7 @@ def main() -> int:
             "sim_time": r["t"],
         }
         states[dn] = h.get_state()
+        results[dn]["newton"] = newton_report(h)
         if args.copy_calibrate:
             src = h.U.clone()
             torch.cuda.synchronize()
@@ -215,6 +230,7 @@ def main() -> int:
                    "limiter": "minmod", "newton_cap": 10, "newton_tol": 1e-8,
                    "parallelism": "single GPU"},
         "sweeps": res["sweeps"],
+        "newton": res["newton"],
         "roofline": roofline,
     }
     if "f32" in results and main_dn != "f32":
@@ -222,7 +238,7 @@ def main() -> int:
         a, b = states["f32"].astype(np.float64), states[main_dn]
         l1 = [float(np.abs(a[k] - b[k]).sum() / max(np.abs(b[k]).sum(), 1e-300)) for k in range(4)]
         line["f32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
-                       "sweeps": r32["sweeps"],
+                       "sweeps": r32["sweeps"], "newton": r32["newton"],
                        "speedup_vs_f64": r32["value"] / res["value"],
                        "rel_l1_vs_f64_after_steps": l1}
     del states

@@ -100,9 +100,17 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   G.h_coef = T(g / (g - 1.0));
   G.pfloor = T(hydro::kCMin * hydro::kCMin / g);
   G.rho_min = T(hydro::kRhoMin);
+  G.inv_rho_min = T(1.0 / hydro::kRhoMin);
   G.c_min = T(hydro::kCMin);
-  G.tol = T(o.tol);
+  // Convergence can only be detected above the arithmetic's rounding noise:
+  // in FP32 the test is floored at 8 ulp of 1.
+  const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
+  G.tol = T(o.tol > tol_floor ? o.tol : tol_floor);
   G.niter = o.niter;
+  // 1/z = 2 gamma / (gamma - 1); an integer exponent (7 for gamma = 1.4) lets
+  // the guess use repeated squaring instead of exp2/log2
+  const double k = std::nearbyint(1.0 / z);
+  G.ipow_k = (k >= 1.0 && k <= 64.0 && std::fabs(1.0 / z - k) <= 1e-12 * k) ? (int)k : 0;
   return G;
 }
 

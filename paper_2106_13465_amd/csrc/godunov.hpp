@@ -2,11 +2,14 @@
 // primitive variables, minmod slopes, MUSCL-Hancock trace, two-shock Riemann
 // solver and interface flux (paper, Section 1 and Figure 5; the numerical
 // readings are stated in include/hydro.h).  Written for gfx950, templated on
-// the arithmetic type (double or float).  Division and square roots are
-// arranged to share reciprocals: per Newton iteration two reciprocal square
-// roots and one division.
+// the arithmetic type (double or float).  Divisions and square roots go
+// through the hardware-approximation layer of fastmath.hpp and are arranged
+// to share reciprocals: per Newton iteration two reciprocal square roots and
+// one reciprocal.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "fastmath.hpp"
 
 namespace hydro {
 
@@ -25,42 +28,17 @@ struct Gas {
   T h_coef;    // gamma / (gamma - 1): enthalpy factor of the energy flux
   T pfloor;    // c_min^2 / gamma: pressure floor per unit density
   T rho_min;
+  T inv_rho_min;
   T c_min;
   T tol;       // Newton convergence test |dp| <= tol * p
   int niter;   // Newton iteration cap
+  int ipow_k;  // 1/z when it is a small integer (7 for gamma = 1.4), else 0
 };
 
 template <typename T>
 struct Prim {
   T r, u, t, p;  // density, normal velocity, transverse velocity, pressure
 };
-
-template <typename T>
-__device__ __forceinline__ T rcp(T x) {
-  return T(1) / x;
-}
-
-template <typename T>
-__device__ __forceinline__ T rsqrt_(T x);
-template <>
-__device__ __forceinline__ double rsqrt_<double>(double x) {
-  return rsqrt(x);
-}
-template <>
-__device__ __forceinline__ float rsqrt_<float>(float x) {
-  return rsqrtf(x);
-}
-
-template <typename T>
-__device__ __forceinline__ T pow_(T x, T y);
-template <>
-__device__ __forceinline__ double pow_<double>(double x, double y) {
-  return pow(x, y);
-}
-template <>
-__device__ __forceinline__ float pow_<float>(float x, float y) {
-  return powf(x, y);
-}
 
 // Conservative (rho, m_n, m_t, E) -> primitive, with floors; also returns
 // 1/rho for the trace.
@@ -69,7 +47,7 @@ __device__ __forceinline__ Prim<T> cons_to_prim(T U0, T Un, T Ut, T E, const Gas
                                                 T& ir) {
   Prim<T> q;
   q.r = fmax(U0, G.rho_min);
-  ir = rcp(q.r);
+  ir = fm::rcp(q.r);
   q.u = Un * ir;
   q.t = Ut * ir;
   T ek = T(0.5) * q.r * (q.u * q.u + q.t * q.t);
@@ -113,25 +91,26 @@ struct Flux {
 
 // Riemann problem at one interface: left state L, right state R.  Returns the
 // flux of the Godunov state at x/t = 0; iters/converged report the Newton
-// solve.  p0 is an optional starting guess (<= 0: two-rarefaction guess).
+// solve.
 template <typename T>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
                                                 const Gas<T>& G, int& iters,
                                                 bool& converged) {
-  const T irL = rcp(L.r), irR = rcp(R.r);
-  const T cL = sqrt(G.g * L.p * irL);
-  const T cR = sqrt(G.g * R.p * irR);
+  const T irL = fm::rcp(L.r), irR = fm::rcp(R.r);
+  const T cL = fm::sqrt(G.g * L.p * irL);
+  const T cR = fm::sqrt(G.g * R.p * irR);
   const T CL = G.g * L.p * L.r;  // Lagrangian sound speed squared
   const T CR = G.g * R.p * R.r;
-  const T ipL = rcp(L.p), ipR = rcp(R.p);
+  const T ipL = fm::rcp(L.p), ipR = fm::rcp(R.p);
   const T pmin = fmin(L.r, R.r) * G.pfloor;
 
-  // two-rarefaction guess
+  // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z)
   T p;
   const T num = cL + cR - G.half_gm1 * (R.u - L.u);
   if (num > T(0)) {
-    T den = cL * pow_(L.p, -G.z) + cR * pow_(R.p, -G.z);
-    p = pow_(num / den, G.inv_z);
+    const T den = cL * fm::pow_pos(L.p, -G.z) + cR * fm::pow_pos(R.p, -G.z);
+    const T ratio = num * fm::rcp(den);
+    p = G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z);
   } else {
     p = pmin;
   }
@@ -144,14 +123,14 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   bool conv = false;
   while (k < G.niter) {
     ++k;
-    T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
-    T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
-    T iWL = rsqrt_(XL), iWR = rsqrt_(XR);
-    T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
-    T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
-    T usL = L.u - (p - L.p) * iWL;
-    T usR = R.u + (p - R.p) * iWR;
-    T dp = (usL - usR) / (izL + izR);
+    const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
+    const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
+    const T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
+    const T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
+    const T usL = L.u - (p - L.p) * iWL;
+    const T usR = R.u + (p - R.p) * iWR;
+    const T dp = (usL - usR) * fm::rcp(izL + izR);
     p = fmax(p + dp, pmin);
     if (fabs(dp) <= G.tol * p) {
       conv = true;
@@ -162,12 +141,12 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   converged = conv;
 
   // star velocity (average of the two sides' estimates) at the final p
-  T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
-  T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
-  T iWL = rsqrt_(XL), iWR = rsqrt_(XR);
-  T usL = L.u - (p - L.p) * iWL;
-  T usR = R.u + (p - R.p) * iWR;
-  T us = T(0.5) * (usL + usR);
+  const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
+  const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+  const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
+  const T usL = L.u - (p - L.p) * iWL;
+  const T usR = R.u + (p - R.p) * iWR;
+  const T us = T(0.5) * (usL + usR);
 
   // upwind side of the contact (u* = 0 -> left)
   const bool left = us >= T(0);
@@ -183,9 +162,9 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
 
   // star density: 1/rho* = 1/rho_o - (p* - p_o)/W_o^2, floored
   T irs = iro + (po - p) * (iWo * iWo);
-  irs = fmin(irs, rcp(G.rho_min));
-  const T rs = rcp(irs);
-  const T cs = fmax(G.c_min, sqrt(G.g * p * irs));
+  irs = fmin(irs, G.inv_rho_min);
+  const T rs = fm::rcp(irs);
+  const T cs = fmax(G.c_min, fm::sqrt(G.g * p * irs));
 
   // outer/inner edge speeds of the wave on that side, positive away from
   // the interface
@@ -208,7 +187,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     gu = us;
     gp = p;
   } else {
-    T f = sout / fmax(sout - sin_, G.c_min);
+    T f = sout * fm::rcp(fmax(sout - sin_, G.c_min));
     f = fmin(fmax(f, T(0)), T(1));
     gr = f * rs + (T(1) - f) * ro;
     gu = f * us + (T(1) - f) * uo;
@@ -228,7 +207,7 @@ template <typename T>
 __device__ __forceinline__ T max_speed(T U0, T U1, T U2, T E, const Gas<T>& G) {
   T ir;
   Prim<T> q = cons_to_prim(U0, U1, U2, E, G, ir);
-  T c = sqrt(G.g * q.p * ir);
+  T c = fm::sqrt(G.g * q.p * ir);
   return fmax(fabs(q.u), fabs(q.t)) + c;
 }
 
