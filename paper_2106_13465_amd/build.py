@@ -1,9 +1,8 @@
 """Build libhydro.so (the C-ABI library) in-tree with hipcc for gfx950.
 
 Flags:
-  -ffp-contract=off   every floating-point operation rounds once, in source
-                      order (no fused multiply-add contraction), on host and
-                      device alike
+  -ffp-contract=      fast for the kernels (multiply-add pairs fuse into one
+                      FMA), off for the host-side C ABI
   -Xclang -target-feature -Xclang -packed-fp32-ops
                       no packed FP32 instructions in device code
 """
@@ -18,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhydro.so")
-SOURCES = ["api.cpp", "kernels.hip"]
+# (source, floating-point contraction)
+SOURCES = [("api.cpp", "off"), ("kernels.hip", "fast")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -27,8 +27,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
-    "-ffp-contract=off",
     "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -39,10 +37,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-x", "hip", *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,6 +48,19 @@ def build(verbose: bool = False) -> str:
              if ln.strip() and "packed-fp32-ops" not in ln and "is not a recognized feature" not in ln]
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
+
+
+def build(verbose: bool = False) -> str:
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src, contract in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        _run([HIPCC, *FLAGS, f"-ffp-contract={contract}", "-fno-gpu-rdc",
+              "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

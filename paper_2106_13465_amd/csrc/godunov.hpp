@@ -104,13 +104,14 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   const T ipL = fm::rcp(L.p), ipR = fm::rcp(R.p);
   const T pmin = fmin(L.r, R.r) * G.pfloor;
 
-  // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z)
+  // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), evaluated as
+  // pL [num / (cL + cR (pR/pL)^-z)]^(1/z): one fractional power
   T p;
   const T num = cL + cR - G.half_gm1 * (R.u - L.u);
   if (num > T(0)) {
-    const T den = cL * fm::pow_pos(L.p, -G.z) + cR * fm::pow_pos(R.p, -G.z);
+    const T den = cL + cR * fm::pow_pos(R.p * ipL, -G.z);
     const T ratio = num * fm::rcp(den);
-    p = G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z);
+    p = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
   } else {
     p = pmin;
   }

@@ -24,18 +24,28 @@
 namespace hydro {
 
 // ------------------------------------------------------------ wave helpers
+// Neighbour exchange by one lane (ds_bpermute through the LDS crossbar; the
+// DPP wavefront shifts measured slower on gfx950).  Edge lanes read their own
+// value; the x-sweep never uses those results.
 template <typename T>
-__device__ __forceinline__ Prim<T> shfl_up1(const Prim<T>& q) {
-  return Prim<T>{__shfl_up(q.r, 1), __shfl_up(q.u, 1), __shfl_up(q.t, 1), __shfl_up(q.p, 1)};
+__device__ __forceinline__ T from_left(T v) {
+  return __shfl_up(v, 1);
 }
 template <typename T>
-__device__ __forceinline__ Prim<T> shfl_down1(const Prim<T>& q) {
-  return Prim<T>{__shfl_down(q.r, 1), __shfl_down(q.u, 1), __shfl_down(q.t, 1),
-                 __shfl_down(q.p, 1)};
+__device__ __forceinline__ T from_right(T v) {
+  return __shfl_down(v, 1);
 }
 template <typename T>
-__device__ __forceinline__ Flux<T> shfl_up1(const Flux<T>& f) {
-  return Flux<T>{__shfl_up(f.m, 1), __shfl_up(f.n, 1), __shfl_up(f.t, 1), __shfl_up(f.e, 1)};
+__device__ __forceinline__ Prim<T> from_left(const Prim<T>& q) {
+  return Prim<T>{from_left(q.r), from_left(q.u), from_left(q.t), from_left(q.p)};
+}
+template <typename T>
+__device__ __forceinline__ Prim<T> from_right(const Prim<T>& q) {
+  return Prim<T>{from_right(q.r), from_right(q.u), from_right(q.t), from_right(q.p)};
+}
+template <typename T>
+__device__ __forceinline__ Flux<T> from_left(const Flux<T>& f) {
+  return Flux<T>{from_left(f.m), from_left(f.n), from_left(f.t), from_left(f.e)};
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -104,8 +114,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(GridArgs<T> a, Gas<T> G, DevSta
     // COMPUTE: primitive variables, slopes, half-step face states
     T ir;
     const Prim<T> q = cons_to_prim(u0, un, ut, e, G, ir);
-    const Prim<T> ql = shfl_up1(q);
-    const Prim<T> qr = shfl_down1(q);
+    const Prim<T> ql = from_left(q);
+    const Prim<T> qr = from_right(q);
     Prim<T> d;
     d.r = minmod(q.r - ql.r, qr.r - q.r);
     d.u = minmod(q.u - ql.u, qr.u - q.u);
@@ -115,11 +125,11 @@ __global__ __launch_bounds__(256) void k_sweep_x(GridArgs<T> a, Gas<T> G, DevSta
     trace(q, ir, d, lam, G, qm, qp);
 
     // Riemann problem at this lane's right interface i+1/2
-    const Prim<T> qm_next = shfl_down1(qm);
+    const Prim<T> qm_next = from_right(qm);
     int iters;
     bool conv;
     const Flux<T> F = riemann_flux(qp, qm_next, G, iters, conv);
-    const Flux<T> Fl = shfl_up1(F);  // interface i-1/2
+    const Flux<T> Fl = from_left(F);  // interface i-1/2
 
     if (STATS) {
       // interfaces owned by this segment: x0-1/2 (first segment only) and the
@@ -189,59 +199,50 @@ __global__ __launch_bounds__(256) void k_sweep_y(GridArgs<T> a, Gas<T> G, DevSta
     return d;
   };
 
-  // prologue: cells y0-2 .. y0+1, faces of y0-1 and y0, interface y0-1/2
-  T irA, irB, irC, irD;
-  const Cell<T> uA = load(y0 - 2);
-  const Cell<T> uB = load(y0 - 1);
-  Cell<T> uC = load(y0);
-  Cell<T> uD = load(y0 + 1);
-  const Prim<T> qA = cons_to_prim(uA.r, uA.n, uA.t, uA.e, G, irA);
-  const Prim<T> qB = cons_to_prim(uB.r, uB.n, uB.t, uB.e, G, irB);
-  Prim<T> qC = cons_to_prim(uC.r, uC.n, uC.t, uC.e, G, irC);
-  Prim<T> qD = cons_to_prim(uD.r, uD.n, uD.t, uD.e, G, irD);
-  Prim<T> qmB, qpB, qmC, qpC;
-  trace(qB, irB, slopes(qA, qB, qC), lam, G, qmB, qpB);
-  trace(qC, irC, slopes(qB, qC, qD), lam, G, qmC, qpC);
-  int iters;
-  bool conv;
-  Flux<T> Fprev = riemann_flux(qpB, qmC, G, iters, conv);
-  if (STATS) count_newton(st, xin && y0 == 0, conv ? iters : 0);
-
+  // One loop body does everything: iteration j READs cell j+2, traces cell
+  // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
+  // four iterations only fill the window (uniform guards), so every step of
+  // the method exists at one code location and an interface shared by two
+  // segments is computed bitwise identically by both.
+  Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
+  Prim<T> q0, q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
+  T ir1, ir2 = T(1);
+  Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
+  Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
   double smax = 0.0;
   int status = 0;
-  for (int j = y0; j < y1; ++j) {
-    // READ cell j+2; COMPUTE faces of j+1 and the flux at j+1/2
-    const Cell<T> uE = load(j + 2);
-    T irE;
-    const Prim<T> qE = cons_to_prim(uE.r, uE.n, uE.t, uE.e, G, irE);
-    Prim<T> qmD, qpD;
-    trace(qD, irD, slopes(qC, qD, qE), lam, G, qmD, qpD);
-    const Flux<T> F = riemann_flux(qpC, qmD, G, iters, conv);
-    if (STATS) count_newton(st, xin, conv ? iters : 0);
-
-    // WRITE cell j
-    const T nr = uC.r + lam * (Fprev.m - F.m);
-    const T nn = uC.n + lam * (Fprev.n - F.n);
-    const T nt = uC.t + lam * (Fprev.t - F.t);
-    const T ne = uC.e + lam * (Fprev.e - F.e);
-    if (xin) {
-      const long long off = (long long)j * a.pitch;
-      out[off] = nr;
-      out[P + off] = nt;
-      out[2 * P + off] = nn;
-      out[3 * P + off] = ne;
-      status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-      if (FUSE_DT) smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
+  for (int j = y0 - 4; j < y1; ++j) {
+    c0 = c1;
+    c1 = c2;
+    q0 = q1;
+    q1 = q2;
+    ir1 = ir2;
+    c2 = load(j + 2);
+    q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
+    if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
+    if (j >= y0 - 1) {
+      int iters;
+      bool conv;
+      F = riemann_flux(qp0, qm1, G, iters, conv);
+      if (STATS) count_newton(st, xin && (j >= y0 || y0 == 0), conv ? iters : 0);
     }
-
-    uC = uD;
-    uD = uE;
-    qC = qD;
-    irC = irD;
-    qD = qE;
-    irD = irE;
-    qpC = qpD;
-    Fprev = F;
+    if (j >= y0) {
+      const T nr = c0.r + lam * (Fm.m - F.m);
+      const T nn = c0.n + lam * (Fm.n - F.n);
+      const T nt = c0.t + lam * (Fm.t - F.t);
+      const T ne = c0.e + lam * (Fm.e - F.e);
+      if (xin) {
+        const long long off = (long long)j * a.pitch;
+        out[off] = nr;
+        out[P + off] = nt;
+        out[2 * P + off] = nn;
+        out[3 * P + off] = ne;
+        status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+        if (FUSE_DT) smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
+      }
+    }
+    qp0 = qp1;
+    Fm = F;
   }
   if (status) atomicOr(&st->status, status);
   if (FUSE_DT) {
