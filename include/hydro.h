@@ -141,6 +141,14 @@ int hydro_get_clock(hydro_t *h, double *t, long *step, double *dt);
 /* Set the device clock (checkpoint restart); dt is kept.  Asynchronous. */
 int hydro_set_clock(hydro_t *h, double t, long step);
 
+/* Advance nsteps time steps by replaying a HIP graph of nsteps consecutive
+ * hydro_step calls, captured on the bound stream at the first call (and again
+ * after hydro_bind, hydro_set_options or a different nsteps).  The bound
+ * stream must not be the legacy default stream (capture is not allowed
+ * there).  Results are bitwise those of nsteps hydro_step calls.
+ * Asynchronous.  nsteps in 1..4096. */
+int hydro_graph_steps(hydro_t *h, int nsteps);
+
 /* Copy the Riemann statistics (synchronises); reset clears them. */
 int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
 

@@ -70,6 +70,7 @@ SIGNATURES = {
     "hydro_get_clock": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_long), _D]),
     "hydro_set_clock": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long]),
     "hydro_riemann_stats": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_stats_t), ctypes.c_int]),
+    "hydro_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
 }

@@ -40,6 +40,9 @@ struct hydro_s {
     hipEvent_t a, b;
   };
   std::vector<Mark> marks;
+  // captured multi-step graph
+  hipGraphExec_t gexec;
+  int graph_steps;
 };
 
 namespace {
@@ -204,6 +207,34 @@ struct PhaseTimer {
   }
 };
 
+void drop_graph(hydro_t* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->graph_steps = 0;
+}
+
+// The kernels of one step: dt from the accumulated max speed, x-sweep U -> V,
+// y-sweep V -> U with the next max speed fused.  Requires st->acc to hold the
+// max speed of U (acc_valid).
+hipError_t enqueue_step_body(hydro_t* h) {
+  const bool f64 = h->dtype == HYDRO_F64;
+  hipError_t e;
+  {
+    PhaseTimer pt(h, HYDRO_PHASE_DT);
+    e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, true, true, h->stream);
+  }
+  if (e != hipSuccess) return e;
+  {
+    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_X);
+    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_X, false, h->U, h->V)
+            : enqueue_sweep<float>(h, HYDRO_DIR_X, false, h->U, h->V);
+  }
+  if (e != hipSuccess) return e;
+  PhaseTimer pt(h, HYDRO_PHASE_SWEEP_Y);
+  return f64 ? enqueue_sweep<double>(h, HYDRO_DIR_Y, true, h->V, h->U)
+             : enqueue_sweep<float>(h, HYDRO_DIR_Y, true, h->V, h->U);
+}
+
 int check_bound(const hydro_t* h) {
   if (!h) return fail(HYDRO_EINVAL, "NULL handle");
   if (!h->bound) return fail(HYDRO_ESTATE, "no state bound (call hydro_bind first)");
@@ -276,6 +307,8 @@ hydro_t* hydro_create(int nx, int ny, double gamma, double cfl, int bc) {
   h->acc_valid = false;
   h->stream = nullptr;
   h->profiling = false;
+  h->gexec = nullptr;
+  h->graph_steps = 0;
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipMalloc((void**)&h->st, sizeof(DevState));
   if (e == hipSuccess)
@@ -297,6 +330,7 @@ void hydro_destroy(hydro_t* h) {
   if (h->st) (void)hipFree(h->st);
   if (h->partials) (void)hipFree(h->partials);
   if (h->V) (void)hipFree(h->V);
+  drop_graph(h);
   for (auto& m : h->marks) {
     (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
@@ -339,6 +373,7 @@ int hydro_bind(hydro_t* h, void* U, long pitch, int dtype, void* hip_stream) {
     }
     h->v_bytes = bytes;
   }
+  drop_graph(h);
   h->U = U;
   h->pitch = pitch;
   h->dtype = dtype;
@@ -364,6 +399,7 @@ int hydro_set_options(hydro_t* h, const hydro_options_t* o) {
   if (o->seg_x < 0 || o->seg_x > 4096) return fail(HYDRO_EINVAL, "seg_x %d", o->seg_x);
   if (o->seg_y < 0 || o->seg_y > (1 << 20)) return fail(HYDRO_EINVAL, "seg_y %d", o->seg_y);
   h->opt = *o;
+  drop_graph(h);
   return HYDRO_OK;
 }
 
@@ -407,28 +443,53 @@ int hydro_step(hydro_t* h) {
   if (rc) return rc;
   DeviceGuard g(h->device);
   hipError_t e = hipSuccess;
-  const bool f64 = h->dtype == HYDRO_F64;
-  {
+  if (!h->acc_valid) {
     PhaseTimer pt(h, HYDRO_PHASE_DT);
-    if (!h->acc_valid) e = f64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
-    if (e == hipSuccess)
-      e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, true, true, h->stream);
+    e = h->dtype == HYDRO_F64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
   }
-  if (e == hipSuccess) {
-    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_X);
-    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_X, false, h->U, h->V)
-            : enqueue_sweep<float>(h, HYDRO_DIR_X, false, h->U, h->V);
-  }
-  if (e == hipSuccess) {
-    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_Y);
-    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_Y, true, h->V, h->U)
-            : enqueue_sweep<float>(h, HYDRO_DIR_Y, true, h->V, h->U);
-  }
+  if (e == hipSuccess) e = enqueue_step_body(h);
   if (e != hipSuccess) {
     h->acc_valid = false;
     return dev_fail(e, "hydro_step");
   }
   h->acc_valid = true;
+  return HYDRO_OK;
+}
+
+int hydro_graph_steps(hydro_t* h, int nsteps) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (nsteps < 1 || nsteps > 4096) return fail(HYDRO_EINVAL, "nsteps %d: 1..4096", nsteps);
+  if (h->stream == nullptr)
+    return fail(HYDRO_ESTATE, "graph capture needs a non-default stream (hydro_bind)");
+  DeviceGuard g(h->device);
+  hipError_t e = hipSuccess;
+  if (!h->acc_valid) {
+    // the graph starts from a valid max speed; compute it eagerly once
+    e = h->dtype == HYDRO_F64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
+    if (e != hipSuccess) return dev_fail(e, "hydro_graph_steps");
+    h->acc_valid = true;
+  }
+  if (!h->gexec || h->graph_steps != nsteps) {
+    drop_graph(h);
+    const bool prof = h->profiling;
+    h->profiling = false;
+    e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = enqueue_step_body(h);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+    h->profiling = prof;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->gexec = nullptr;
+      return dev_fail(e, "graph capture");
+    }
+    h->graph_steps = nsteps;
+  }
+  e = hipGraphLaunch(h->gexec, h->stream);
+  if (e != hipSuccess) return dev_fail(e, "hipGraphLaunch");
   return HYDRO_OK;
 }
 

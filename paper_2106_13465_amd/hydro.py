@@ -36,7 +36,8 @@ class Hydro:
 
     The state lives in ``self.U`` (a torch tensor [4, ny, pitch] on the current
     HIP device; planes rho, rho u, rho v, E); ``self.state`` is its [4, ny, nx]
-    view.  Work runs on torch's current stream at bind time.
+    view.  Work runs on a stream of the handle's own (a new torch stream at the
+    default priority unless one is given), so the step can be graph-captured.
     """
 
     def __init__(self, nx: int, ny: int, gamma: float = 1.4, cfl: float = 0.8,
@@ -57,7 +58,7 @@ class Hydro:
                 raise HydroError(_lib.HYDRO_EINVAL, _lib.last_error())
             self.pitch = int(pitch) if pitch is not None else _padded_pitch(self.nx, dtype)
             self.U = torch.zeros((4, self.ny, self.pitch), dtype=dtype, device=self.device)
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             self._bind()
 
     # ------------------------------------------------------------ plumbing
@@ -67,6 +68,7 @@ class Hydro:
 
     def close(self):
         if getattr(self, "handle", None):
+            self.stream.synchronize()
             self.lib.hydro_destroy(self.handle)
             self.handle = None
 
@@ -89,14 +91,19 @@ class Hydro:
         t = torch.as_tensor(np.asarray(U) if not isinstance(U, torch.Tensor) else U)
         if tuple(t.shape) != (4, self.ny, self.nx):
             raise ValueError(f"state shape {tuple(t.shape)} != (4, {self.ny}, {self.nx})")
-        with torch.cuda.stream(self.stream):
-            self.state.copy_(t.to(device=self.device, dtype=self.dtype, non_blocking=False))
         self.stream.synchronize()
+        torch.cuda.synchronize(self.device)
+        self.state.copy_(t.to(device=self.device, dtype=self.dtype))
+        torch.cuda.synchronize(self.device)
         check(self.lib.hydro_invalidate(self.handle))
 
     def get_state(self) -> np.ndarray:
         self.stream.synchronize()
         return self.state.detach().to("cpu").numpy().copy()
+
+    def graph_steps(self, nsteps: int) -> None:
+        """nsteps time steps as one replay of a captured HIP graph."""
+        check(self.lib.hydro_graph_steps(self.handle, int(nsteps)))
 
     # ------------------------------------------------------------ ABI calls
     def set_options(self, **kw) -> None:

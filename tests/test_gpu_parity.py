@@ -1,6 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on the
-same seeded inputs.  FP64 bar: per variable max|U_gpu - U_oracle| / max|U_oracle|
-<= 1e-12 (dt <= 1e-13 relative)."""
+same seeded inputs.  FP64 bar: per variable max|U_gpu - U_oracle| / scale <= 1e-12
+(dt <= 1e-13 relative), where the scale of rho and E is their max magnitude and
+the scale of a momentum component is max sqrt(2 rho E), the momentum scale of the
+state (|m| <= sqrt(2 rho E) in every cell).  A cell's momentum update is the
+difference of the pressure impulses through its two faces, which at a point
+blast exceed the cell's momentum by orders of magnitude, so its rounding error
+lives on that scale rather than on max|m|."""
 import math
 
 import numpy as np
@@ -13,13 +18,17 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 
 
+def var_scales(b):
+    """Scale of each conserved variable of the reference state b [4, ...]."""
+    mom = np.max(np.sqrt(2.0 * np.abs(b[0]) * np.abs(b[3])))
+    scales = [np.max(np.abs(b[0])), max(mom, np.max(np.abs(b[1]))),
+              max(mom, np.max(np.abs(b[2]))), np.max(np.abs(b[3]))]
+    return [s if s > 0 else 1.0 for s in scales]
+
+
 def rel_err(a, b):
     """Per-variable normwise relative error, max over the 4 variables."""
-    errs = []
-    for k in range(4):
-        scale = np.max(np.abs(b[k]))
-        errs.append(np.max(np.abs(a[k] - b[k])) / (scale if scale > 0 else 1.0))
-    return max(errs)
+    return max(np.max(np.abs(a[k] - b[k])) / s for k, s in enumerate(var_scales(b)))
 
 
 @pytest.fixture(scope="module")
@@ -158,3 +167,82 @@ def test_fp32_l1(torch_cuda, orc, bc):
         l1 = np.abs(got[k] - ref[k]).sum() / max(np.abs(ref[k]).sum(), 1e-300)
         print("fp32 L1", k, l1)
         assert l1 < 1e-5
+
+
+def test_graph_replay_matches_eager(torch_cuda, orc):
+    """A captured multi-step graph, replayed several times with eager steps and
+    host synchronisation in between, matches eager stepping bitwise after
+    every replay."""
+    U = inputs.random_states(200, 150, seed=44, rough=0.5)
+    a = make(torch_cuda, U, 3)
+    b = make(torch_cuda, U, 3)
+    for rep in range(4):
+        a.graph_steps(3)
+        b.step(3)
+        ga, gb = a.get_state(), b.get_state()
+        assert np.array_equal(ga, gb), f"replay {rep}"
+        assert a.clock()[1] == b.clock()[1] == 3 * (rep + 1) + rep
+        a.step(1)
+        b.step(1)
+    ref = U.copy()
+    c = orc.cfg(bc=3)
+    for _ in range(16):
+        orc.step(ref, c)
+    assert a.clock()[1] == 16
+    assert rel_err(a.get_state(), ref) <= TOL64
+
+
+def test_error_paths(torch_cuda):
+    """Invalid arguments come back as error codes with a message."""
+    from paper_2106_13465_amd import _lib
+    from paper_2106_13465_amd.hydro import Hydro, HydroError
+
+    lib = _lib.load()
+    assert not lib.hydro_create(1, 5, 1.4, 0.8, 3)
+    assert "must be >= 2" in _lib.last_error()
+    assert not lib.hydro_create(8, 8, 1.0, 0.8, 3)
+    assert not lib.hydro_create(8, 8, 1.4, 1.5, 3)
+    assert not lib.hydro_create(8, 8, 1.4, 0.8, 7)
+    h = lib.hydro_create(8, 8, 1.4, 0.8, 3)
+    assert h
+    assert lib.hydro_step(h) == _lib.HYDRO_ESTATE
+    assert lib.hydro_sweep(h, 0) == _lib.HYDRO_ESTATE
+    assert lib.hydro_compute_dt(h) == _lib.HYDRO_ESTATE
+    lib.hydro_destroy(h)
+    g = Hydro(16, 16, 1.4, 0.8, "periodic")
+    with pytest.raises(HydroError):
+        g.sweep(5)
+    with pytest.raises(HydroError):
+        g.set_options(niter=0)
+    with pytest.raises(HydroError):
+        g.set_options(tol=-1.0)
+    with pytest.raises(HydroError):
+        g.graph_steps(0)
+    # a non-finite state is latched and reported at the next synchronising call
+    U = inputs.uniform(16, 16)
+    U[3, 5, 5] = np.nan
+    g.set_state(U)
+    g.step(1)
+    with pytest.raises(HydroError) as ei:
+        g.totals()
+    assert ei.value.code == _lib.HYDRO_ENONPHYS
+    g.set_state(inputs.uniform(16, 16))
+    g.step(1)
+    assert np.all(np.isfinite(g.totals()))
+
+
+def test_checkpoint_restart_bitwise(torch_cuda, orc):
+    """2N steps equal N steps, a save of (state, clock), a fresh handle and N
+    more steps, bitwise."""
+    U = inputs.random_smooth(96, 80, seed=45, amp=0.5)
+    a = make(torch_cuda, U, 1)
+    a.step(8)
+    full = a.get_state()
+    b = make(torch_cuda, U, 1)
+    b.step(4)
+    saved, (t, n, _) = b.get_state(), b.clock()
+    c = make(torch_cuda, saved, 1)
+    c.set_clock(t, n)
+    c.step(4)
+    assert np.array_equal(c.get_state(), full)
+    assert c.clock()[1] == 8 and abs(c.clock()[0] - a.clock()[0]) <= 1e-15 * a.clock()[0]
