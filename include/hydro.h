@@ -87,6 +87,18 @@ typedef struct {
   long long fallbacks;                   /* learned guess rejected          */
 } hydro_stats_t;
 
+/* Launch shape chosen by the autotuner (hydro_autotune / hydro_batch_autotune).
+ * Results never depend on it. */
+typedef struct {
+  int seg_x;          /* x-sweep: 60-cell segments per wave item                 */
+  int seg_y;          /* y-sweep: rows marched per wave item                     */
+  unsigned blocks_x;  /* 0: one 4-wave block per 4 items; else persistent blocks */
+  unsigned blocks_y;
+  double ms_x, ms_y;  /* best measured sweep times (ms); -1 when reused          */
+  int candidates;     /* launch shapes timed                                     */
+  int cached;         /* 1: reused an earlier tuning of the same grid shapes     */
+} hydro_tune_t;
+
 /* Create a solver for an nx x ny grid (both >= 2) of an ideal gas with ratio
  * of specific heats gamma > 1, Courant number 0 < cfl <= 1 and boundary type
  * bc (one of HYDRO_BC_*, applied on all four sides).  Allocates the handle's
@@ -152,6 +164,13 @@ int hydro_graph_steps(hydro_t *h, int nsteps);
 /* Copy the Riemann statistics (synchronises); reset clears them. */
 int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
 
+/* Time candidate launch shapes (segments per item, persistent block counts)
+ * of both sweeps on the bound state and keep the fastest.  U is not
+ * modified; the fused max speed is invalidated.  use_cache reuses the result
+ * of an earlier tuning of the same grid shapes and dtype in this process.
+ * Synchronises.  out may be NULL. */
+int hydro_autotune(hydro_t *h, hydro_tune_t *out, int use_cache);
+
 /* Kernel timing.  While enabled, hydro_step records a HIP event pair on the
  * bound stream around each of its phases (dt, x-sweep, y-sweep), except
  * under stream capture.  hydro_get_profile synchronises, returns the summed
@@ -161,6 +180,49 @@ enum { HYDRO_PHASE_DT = 0, HYDRO_PHASE_SWEEP_X = 1, HYDRO_PHASE_SWEEP_Y = 2, HYD
 int hydro_set_profiling(hydro_t *h, int enable);
 int hydro_get_profile(hydro_t *h, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
                       int reset);
+
+/* ------------------------------------------------------------------------
+ * Batches: n independent grids of uneven sizes advanced together, one kernel
+ * launch per sweep over all of them (persistent wave loop over a work list
+ * of (grid, segment) items), each grid with its own dt, clock and status.
+ * Same numerics and readings as a single grid.
+ *
+ * LAYOUT.  All grids live in one caller-owned device buffer; grid g occupies
+ * [offsets[g], offsets[g] + 4 * ny[g] * pitches[g]) elements with the layout
+ * of a single grid ([4][ny][pitch], x fastest).  hydro_batch_layout gives the
+ * offsets and pitches the library uses (rows padded to 256 bytes).
+ * ------------------------------------------------------------------------ */
+typedef struct hydro_batch_s hydro_batch_t;
+
+/* n >= 1 grids; nx[g], ny[g] >= 2; bc[g] one of HYDRO_BC_*; NULL on error. */
+hydro_batch_t *hydro_batch_create(int n, const int *nx, const int *ny, double gamma,
+                                  double cfl, const int *bc);
+void hydro_batch_destroy(hydro_batch_t *b);
+/* Returns the elements per state buffer for dtype and fills offsets[n] and
+ * pitches[n] (either may be NULL); negative on error. */
+long long hydro_batch_layout(const hydro_batch_t *b, int dtype, long long *offsets,
+                             long *pitches);
+/* Bind the packed state (layout above) and stream; allocates the second
+ * buffer. */
+int hydro_batch_bind(hydro_batch_t *b, void *U, int dtype, void *hip_stream);
+int hydro_batch_set_options(hydro_batch_t *b, const hydro_options_t *o);
+int hydro_batch_invalidate(hydro_batch_t *b);
+/* Per-grid dt into dt[n] (may be NULL); synchronises. */
+int hydro_batch_compute_dt(hydro_batch_t *b, double *dt);
+/* One time step of every grid (its own dt); asynchronous. */
+int hydro_batch_step(hydro_batch_t *b);
+/* nsteps steps of every grid as one replay of a captured HIP graph. */
+int hydro_batch_graph_steps(hydro_batch_t *b, int nsteps);
+/* out[4 g + k]: totals of grid g; synchronises. */
+int hydro_batch_totals(hydro_batch_t *b, double *out);
+/* Per-grid clocks (arrays of n, any may be NULL); synchronises. */
+int hydro_batch_get_clock(hydro_batch_t *b, double *t, long *step, double *dt);
+/* Riemann statistics summed over the grids; synchronises. */
+int hydro_batch_riemann_stats(hydro_batch_t *b, hydro_stats_t *s, int reset);
+int hydro_batch_autotune(hydro_batch_t *b, hydro_tune_t *out, int use_cache);
+int hydro_batch_set_profiling(hydro_batch_t *b, int enable);
+int hydro_batch_get_profile(hydro_batch_t *b, double ms[HYDRO_NPHASES],
+                            long long launches[HYDRO_NPHASES], int reset);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,19 @@ class hydro_stats_t(ctypes.Structure):
     ]
 
 
+class hydro_tune_t(ctypes.Structure):
+    _fields_ = [
+        ("seg_x", ctypes.c_int),
+        ("seg_y", ctypes.c_int),
+        ("blocks_x", ctypes.c_uint),
+        ("blocks_y", ctypes.c_uint),
+        ("ms_x", ctypes.c_double),
+        ("ms_y", ctypes.c_double),
+        ("candidates", ctypes.c_int),
+        ("cached", ctypes.c_int),
+    ]
+
+
 class HydroError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -54,6 +67,9 @@ class HydroError(RuntimeError):
 
 _vp = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_L = ctypes.POINTER(ctypes.c_long)
+_LL = ctypes.POINTER(ctypes.c_longlong)
 
 SIGNATURES = {
     "hydro_create": (_vp, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
@@ -73,6 +89,24 @@ SIGNATURES = {
     "hydro_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
+    "hydro_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_tune_t), ctypes.c_int]),
+    # batches
+    "hydro_batch_create": (_vp, [ctypes.c_int, _I, _I, ctypes.c_double, ctypes.c_double, _I]),
+    "hydro_batch_destroy": (None, [_vp]),
+    "hydro_batch_layout": (ctypes.c_longlong, [_vp, ctypes.c_int, _LL, _L]),
+    "hydro_batch_bind": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
+    "hydro_batch_set_options": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_options_t)]),
+    "hydro_batch_invalidate": (ctypes.c_int, [_vp]),
+    "hydro_batch_compute_dt": (ctypes.c_int, [_vp, _D]),
+    "hydro_batch_step": (ctypes.c_int, [_vp]),
+    "hydro_batch_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "hydro_batch_totals": (ctypes.c_int, [_vp, _D]),
+    "hydro_batch_get_clock": (ctypes.c_int, [_vp, _D, _L, _D]),
+    "hydro_batch_riemann_stats": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_stats_t), ctypes.c_int]),
+    "hydro_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_tune_t), ctypes.c_int]),
+    "hydro_batch_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "hydro_batch_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong),
+                                               ctypes.c_int]),
 }
 
 _lib = None

@@ -1,6 +1,7 @@
-// api.cpp -- the C ABI of include/hydro.h: handle life cycle, argument
-// validation, error reporting, and the order in which a time step enqueues
-// its kernels (dt, x-sweep, y-sweep; paper, Figure 5).
+// api.cpp -- the C ABI of include/hydro.h: argument validation, error
+// reporting and thin wrappers over hydro::Plan.  A single-grid handle is a
+// plan with one grid bound at offset 0 with the caller's pitch; a batch handle
+// binds the packed layout of hydro_batch_layout.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,38 +13,10 @@
 
 #include "hydro.h"
 #include "launch.hpp"
+#include "plan.hpp"
 
-using hydro::DevState;
-using hydro::Gas;
-using hydro::GridArgs;
-
-struct hydro_s {
-  int nx, ny, bc;
-  double gamma, cfl, h;
-  hydro_options_t opt;
-  int device;
-  DevState* st;       // device scratch
-  double* partials;   // device, totals_blocks() * 4
-  void* U;            // bound state (caller-owned)
-  void* V;            // second state buffer of the same size (handle-owned)
-  size_t v_bytes;
-  long pitch;
-  int dtype;
-  hipStream_t stream;
-  bool bound;
-  bool acc_valid;     // st->acc holds the max speed of the current U
-  // kernel timing: event pairs recorded around the phases of hydro_step
-  bool profiling;
-  std::vector<hipEvent_t> ev_pool;
-  struct Mark {
-    int phase;
-    hipEvent_t a, b;
-  };
-  std::vector<Mark> marks;
-  // captured multi-step graph
-  hipGraphExec_t gexec;
-  int graph_steps;
-};
+struct hydro_s : hydro::Plan {};
+struct hydro_batch_s : hydro::Plan {};
 
 namespace {
 
@@ -61,16 +34,11 @@ int dev_fail(hipError_t e, const char* what) {
   return fail(HYDRO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Makes the handle's device current for the duration of a call.
+// Makes the plan's device current for the duration of a call.
 struct DeviceGuard {
   int prev = -1;
-  bool ok = true;
   explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) {
-      ok = false;
-      return;
-    }
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
     int cur;
@@ -78,319 +46,53 @@ struct DeviceGuard {
   }
 };
 
-hydro_options_t default_options() {
-  hydro_options_t o;
-  std::memset(&o, 0, sizeof o);
-  o.niter = 10;
-  o.tol = 1e-8;
-  o.guess = HYDRO_GUESS_PTR;
-  o.stats = 0;
-  o.seg_x = 0;
-  o.seg_y = 0;
-  return o;
-}
-
-template <typename T>
-Gas<T> make_gas(double g, const hydro_options_t& o) {
-  Gas<T> G;
-  const double z = (g - 1.0) / (2.0 * g);
-  G.g = T(g);
-  G.gm1 = T(g - 1.0);
-  G.gs = T((g + 1.0) / (2.0 * g));
-  G.z = T(z);
-  G.inv_z = T(1.0 / z);
-  G.half_gm1 = T(0.5 * (g - 1.0));
-  G.h_coef = T(g / (g - 1.0));
-  G.pfloor = T(hydro::kCMin * hydro::kCMin / g);
-  G.rho_min = T(hydro::kRhoMin);
-  G.inv_rho_min = T(1.0 / hydro::kRhoMin);
-  G.c_min = T(hydro::kCMin);
-  // Convergence can only be detected above the arithmetic's rounding noise:
-  // in FP32 the test is floored at 8 ulp of 1.
-  const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
-  G.tol = T(o.tol > tol_floor ? o.tol : tol_floor);
-  G.niter = o.niter;
-  // 1/z = 2 gamma / (gamma - 1); an integer exponent (7 for gamma = 1.4) lets
-  // the guess use repeated squaring instead of exp2/log2
-  const double k = std::nearbyint(1.0 / z);
-  G.ipow_k = (k >= 1.0 && k <= 64.0 && std::fabs(1.0 / z - k) <= 1e-12 * k) ? (int)k : 0;
-  return G;
-}
-
-// Sweeps never update in place: each reads one buffer and writes the other.
-template <typename T>
-GridArgs<T> grid_args(const hydro_t* h, const void* src, void* dst) {
-  GridArgs<T> a;
-  a.src = static_cast<const T*>(src);
-  a.dst = static_cast<T*>(dst);
-  a.pitch = (int)h->pitch;
-  a.plane = (long long)h->pitch * h->ny;
-  a.nx = h->nx;
-  a.ny = h->ny;
-  a.bc = h->bc;
-  a.h = h->h;
-  a.cfl = h->cfl;
-  return a;
-}
-
-int seg_x_of(const hydro_t* h) { return h->opt.seg_x > 0 ? h->opt.seg_x : 1; }
-int seg_y_of(const hydro_t* h) {
-  int s = h->opt.seg_y > 0 ? h->opt.seg_y : 128;
-  return s < h->ny ? s : h->ny;
-}
-
-template <typename T>
-hipError_t enqueue_sweep(hydro_t* h, int dir, bool fuse_dt, const void* src, void* dst) {
-  const GridArgs<T> a = grid_args<T>(h, src, dst);
-  const Gas<T> G = make_gas<T>(h->gamma, h->opt);
-  if (dir == HYDRO_DIR_X)
-    return hydro::launch_sweep_x<T>(a, G, h->st, seg_x_of(h), h->opt.stats != 0, h->stream);
-  return hydro::launch_sweep_y<T>(a, G, h->st, seg_y_of(h), fuse_dt, h->opt.stats != 0,
-                                  h->stream);
-}
-
-template <typename T>
-hipError_t enqueue_max_speed(hydro_t* h) {
-  hipError_t e = hydro::launch_reset_acc(h->st, h->stream);
-  if (e != hipSuccess) return e;
-  return hydro::launch_max_speed<T>(grid_args<T>(h, h->U, nullptr),
-                                    make_gas<T>(h->gamma, h->opt), h->st, h->stream);
-}
-
-template <typename T>
-hipError_t enqueue_totals(hydro_t* h) {
-  return hydro::launch_totals<T>(grid_args<T>(h, h->U, nullptr), h->partials, h->st,
-                                 h->stream);
-}
-
-// One standalone sweep: U -> V, then V copied back into U.
-template <typename T>
-hipError_t enqueue_single_sweep(hydro_t* h, int dir) {
-  hipError_t e = enqueue_sweep<T>(h, dir, false, h->U, h->V);
-  if (e != hipSuccess) return e;
-  return hydro::launch_copy<T>(grid_args<T>(h, h->V, h->U), h->stream);
-}
-
-// Event pair around one phase of a step (no-op unless profiling and the
-// stream is not being captured).
-struct PhaseTimer {
-  hydro_t* h;
-  int phase;
-  hipEvent_t a = nullptr, b = nullptr;
-  PhaseTimer(hydro_t* h_, int phase_) : h(h_), phase(phase_) {
-    if (!h->profiling) return;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-      return;
-    a = take();
-    b = take();
-    if (a && b) (void)hipEventRecord(a, h->stream);
-  }
-  hipEvent_t take() {
-    hipEvent_t e = nullptr;
-    if (!h->ev_pool.empty()) {
-      e = h->ev_pool.back();
-      h->ev_pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-      e = nullptr;
-    }
-    return e;
-  }
-  ~PhaseTimer() {
-    if (a && b) {
-      (void)hipEventRecord(b, h->stream);
-      h->marks.push_back({phase, a, b});
-    } else {
-      if (a) h->ev_pool.push_back(a);
-      if (b) h->ev_pool.push_back(b);
-    }
-  }
-};
-
-void drop_graph(hydro_t* h) {
-  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-  h->gexec = nullptr;
-  h->graph_steps = 0;
-}
-
-// The kernels of one step: dt from the accumulated max speed, x-sweep U -> V,
-// y-sweep V -> U with the next max speed fused.  Requires st->acc to hold the
-// max speed of U (acc_valid).
-hipError_t enqueue_step_body(hydro_t* h) {
-  const bool f64 = h->dtype == HYDRO_F64;
-  hipError_t e;
-  {
-    PhaseTimer pt(h, HYDRO_PHASE_DT);
-    e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, true, true, h->stream);
-  }
-  if (e != hipSuccess) return e;
-  {
-    PhaseTimer pt(h, HYDRO_PHASE_SWEEP_X);
-    e = f64 ? enqueue_sweep<double>(h, HYDRO_DIR_X, false, h->U, h->V)
-            : enqueue_sweep<float>(h, HYDRO_DIR_X, false, h->U, h->V);
-  }
-  if (e != hipSuccess) return e;
-  PhaseTimer pt(h, HYDRO_PHASE_SWEEP_Y);
-  return f64 ? enqueue_sweep<double>(h, HYDRO_DIR_Y, true, h->V, h->U)
-             : enqueue_sweep<float>(h, HYDRO_DIR_Y, true, h->V, h->U);
-}
-
-int check_bound(const hydro_t* h) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  if (!h->bound) return fail(HYDRO_ESTATE, "no state bound (call hydro_bind first)");
+int check_grid(int nx, int ny, int bc) {
+  if (nx < 2 || ny < 2) return fail(HYDRO_EINVAL, "grid %d x %d: both sides must be >= 2", nx, ny);
+  if (nx > (1 << 28) || ny > (1 << 28) || (long long)nx * ny >= (1ll << 38))
+    return fail(HYDRO_EINVAL, "grid %d x %d too large", nx, ny);
+  if (bc != HYDRO_BC_REFLECT && bc != HYDRO_BC_OUTFLOW && bc != HYDRO_BC_PERIODIC)
+    return fail(HYDRO_EINVAL, "bc = %d: not a HYDRO_BC_* value", bc);
   return HYDRO_OK;
 }
 
-// Copies the device scratch to the host after the stream drains; reports a
-// latched non-physical state once and clears it.
-int sync_state(hydro_t* h, DevState* out) {
-  hipError_t e = hipMemcpyAsync(out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync");
-  e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
-  if (out->status != 0) {
-    int zero = 0;
-    e = hipMemcpyAsync(&h->st->status, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return dev_fail(e, "status reset");
-    return fail(HYDRO_ENONPHYS, "a sweep produced a non-physical state (status 0x%x)",
-                out->status);
-  }
+int check_gas(double gamma, double cfl) {
+  if (!(gamma > 1.0) || !std::isfinite(gamma))
+    return fail(HYDRO_EINVAL, "gamma = %g: must be > 1", gamma);
+  if (!(cfl > 0.0 && cfl <= 1.0)) return fail(HYDRO_EINVAL, "cfl = %g: must be in (0, 1]", cfl);
   return HYDRO_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* hydro_last_error(void) { return g_err; }
-
-hydro_t* hydro_create(int nx, int ny, double gamma, double cfl, int bc) {
-  if (nx < 2 || ny < 2) {
-    fail(HYDRO_EINVAL, "grid %d x %d: both sides must be >= 2", nx, ny);
+template <typename H>
+H* create_plan(int n, const int* nx, const int* ny, double gamma, double cfl, const int* bc) {
+  if (n < 1 || !nx || !ny || !bc) {
+    fail(HYDRO_EINVAL, "batch of %d grids (or NULL sizes)", n);
     return nullptr;
   }
-  if ((long long)nx * ny * 4 >= (1ll << 40)) {
-    fail(HYDRO_EINVAL, "grid %d x %d too large", nx, ny);
-    return nullptr;
-  }
-  if (!(gamma > 1.0) || !std::isfinite(gamma)) {
-    fail(HYDRO_EINVAL, "gamma = %g: must be > 1", gamma);
-    return nullptr;
-  }
-  if (!(cfl > 0.0 && cfl <= 1.0)) {
-    fail(HYDRO_EINVAL, "cfl = %g: must be in (0, 1]", cfl);
-    return nullptr;
-  }
-  if (bc != HYDRO_BC_REFLECT && bc != HYDRO_BC_OUTFLOW && bc != HYDRO_BC_PERIODIC) {
-    fail(HYDRO_EINVAL, "bc = %d: not a HYDRO_BC_* value", bc);
-    return nullptr;
-  }
-  hydro_t* h = new (std::nothrow) hydro_s();
+  for (int g = 0; g < n; ++g)
+    if (check_grid(nx[g], ny[g], bc[g])) return nullptr;
+  if (check_gas(gamma, cfl)) return nullptr;
+  H* h = new (std::nothrow) H();
   if (!h) {
     fail(HYDRO_ENOMEM, "host allocation failed");
     return nullptr;
   }
-  h->nx = nx;
-  h->ny = ny;
-  h->bc = bc;
-  h->gamma = gamma;
-  h->cfl = cfl;
-  h->h = 1.0 / (double)(nx > ny ? nx : ny);
-  h->opt = default_options();
-  h->st = nullptr;
-  h->partials = nullptr;
-  h->U = nullptr;
-  h->V = nullptr;
-  h->v_bytes = 0;
-  h->bound = false;
-  h->acc_valid = false;
-  h->stream = nullptr;
-  h->profiling = false;
-  h->gexec = nullptr;
-  h->graph_steps = 0;
-  hipError_t e = hipGetDevice(&h->device);
-  if (e == hipSuccess) e = hipMalloc((void**)&h->st, sizeof(DevState));
-  if (e == hipSuccess)
-    e = hipMalloc((void**)&h->partials, sizeof(double) * 4 * hydro::totals_blocks());
-  if (e == hipSuccess) e = hipMemset(h->st, 0, sizeof(DevState));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipError_t e = h->init(n, nx, ny, bc, gamma, cfl);
   if (e != hipSuccess) {
-    dev_fail(e, "hydro_create");
-    hydro_destroy(h);
+    dev_fail(e, "create");
+    delete h;
     return nullptr;
   }
   return h;
 }
 
-void hydro_destroy(hydro_t* h) {
-  if (!h) return;
-  DeviceGuard g(h->device);
-  if (h->bound && h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->st) (void)hipFree(h->st);
-  if (h->partials) (void)hipFree(h->partials);
-  if (h->V) (void)hipFree(h->V);
-  drop_graph(h);
-  for (auto& m : h->marks) {
-    (void)hipEventDestroy(m.a);
-    (void)hipEventDestroy(m.b);
-  }
-  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
-  delete h;
-}
-
-int hydro_bind(hydro_t* h, void* U, long pitch, int dtype, void* hip_stream) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  if (!U) return fail(HYDRO_EINVAL, "NULL state pointer");
-  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return fail(HYDRO_EINVAL, "dtype %d", dtype);
-  if (pitch < h->nx) return fail(HYDRO_EINVAL, "pitch %ld < nx %d", pitch, h->nx);
-  if ((long long)pitch * h->ny * 4 >= (1ll << 40) || pitch > (1l << 30))
-    return fail(HYDRO_EINVAL, "pitch %ld too large", pitch);
-  const size_t elem = dtype == HYDRO_F64 ? 8 : 4;
-  if (((uintptr_t)U) % elem != 0) return fail(HYDRO_EINVAL, "state pointer misaligned");
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, U) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-    (void)hipGetLastError();
-    return fail(HYDRO_EINVAL, "state pointer is not device memory");
-  }
-  if (attr.device != h->device)
-    return fail(HYDRO_EINVAL, "state on device %d, handle on device %d", attr.device, h->device);
-  const size_t bytes = elem * 4 * (size_t)pitch * (size_t)h->ny;
-  if (h->v_bytes != bytes) {
-    DeviceGuard g(h->device);
-    if (h->V) {
-      if (h->bound && h->stream) (void)hipStreamSynchronize(h->stream);
-      (void)hipFree(h->V);
-      h->V = nullptr;
-      h->v_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&h->V, bytes);
-    if (e != hipSuccess) {
-      h->V = nullptr;
-      h->bound = false;
-      return fail(HYDRO_ENOMEM, "second state buffer (%zu bytes): %s", bytes,
-                  hipGetErrorString(e));
-    }
-    h->v_bytes = bytes;
-  }
-  drop_graph(h);
-  h->U = U;
-  h->pitch = pitch;
-  h->dtype = dtype;
-  h->stream = (hipStream_t)hip_stream;
-  h->bound = true;
-  h->acc_valid = false;
+int check_bound(const hydro::Plan* p) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  if (!p->bound) return fail(HYDRO_ESTATE, "no state bound (bind first)");
   return HYDRO_OK;
 }
 
-int hydro_invalidate(hydro_t* h) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  h->acc_valid = false;
-  return HYDRO_OK;
-}
-
-int hydro_set_options(hydro_t* h, const hydro_options_t* o) {
-  if (!h || !o) return fail(HYDRO_EINVAL, "NULL argument");
+int check_options(const hydro_options_t* o) {
+  if (!o) return fail(HYDRO_EINVAL, "NULL options");
   if (o->niter < 1 || o->niter > HYDRO_MAX_NITER)
     return fail(HYDRO_EINVAL, "niter %d: must be in 1..%d", o->niter, HYDRO_MAX_NITER);
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(HYDRO_EINVAL, "tol %g", o->tol);
@@ -398,174 +100,158 @@ int hydro_set_options(hydro_t* h, const hydro_options_t* o) {
     return fail(HYDRO_EINVAL, "guess %d not available on this handle", o->guess);
   if (o->seg_x < 0 || o->seg_x > 4096) return fail(HYDRO_EINVAL, "seg_x %d", o->seg_x);
   if (o->seg_y < 0 || o->seg_y > (1 << 20)) return fail(HYDRO_EINVAL, "seg_y %d", o->seg_y);
-  h->opt = *o;
-  drop_graph(h);
   return HYDRO_OK;
 }
 
-int hydro_get_options(const hydro_t* h, hydro_options_t* o) {
-  if (!h || !o) return fail(HYDRO_EINVAL, "NULL argument");
-  *o = h->opt;
-  return HYDRO_OK;
+// Copies the per-grid states after the stream drains; reports a latched
+// non-physical state once and clears it.
+int sync_states(hydro::Plan* p, std::vector<hydro::DevState>& s) {
+  hipError_t e = p->sync_states(s);
+  if (e != hipSuccess) return dev_fail(e, "synchronise");
+  int bad = -1;
+  for (int g = 0; g < p->n; ++g)
+    if (s[g].status != 0) bad = g;
+  if (bad < 0) return HYDRO_OK;
+  for (int g = 0; g < p->n; ++g) {
+    if (s[g].status == 0) continue;
+    int zero = 0;
+    e = hipMemcpyAsync(&p->st[g].status, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return dev_fail(e, "status reset");
+  }
+  return fail(HYDRO_ENONPHYS, "a sweep produced a non-physical state (grid %d, status 0x%x)", bad,
+              s[bad].status);
 }
 
-double hydro_compute_dt(hydro_t* h) {
-  int rc = check_bound(h);
+int do_compute_dt(hydro::Plan* p, double* dt) {
+  int rc = check_bound(p);
   if (rc) return rc;
-  DeviceGuard g(h->device);
-  hipError_t e = h->dtype == HYDRO_F64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
-  if (e == hipSuccess) e = hydro::launch_finalize_dt(h->st, h->cfl, h->h, false, false, h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hydro_compute_dt");
-  DevState s;
-  rc = sync_state(h, &s);
+  DeviceGuard g(p->device);
+  hipError_t e = p->enqueue_max_speed();
+  if (e == hipSuccess) e = p->enqueue_finalize(false, false);
+  if (e != hipSuccess) return dev_fail(e, "compute_dt");
+  std::vector<hydro::DevState> s;
+  rc = sync_states(p, s);
   if (rc) {
-    h->acc_valid = false;
+    p->acc_valid = false;
     return rc;
   }
-  h->acc_valid = true;
-  return s.dt;
-}
-
-int hydro_sweep(hydro_t* h, int dir) {
-  int rc = check_bound(h);
-  if (rc) return rc;
-  if (dir != HYDRO_DIR_X && dir != HYDRO_DIR_Y) return fail(HYDRO_EINVAL, "dir %d", dir);
-  DeviceGuard g(h->device);
-  hipError_t e = h->dtype == HYDRO_F64 ? enqueue_single_sweep<double>(h, dir)
-                                       : enqueue_single_sweep<float>(h, dir);
-  h->acc_valid = false;
-  if (e != hipSuccess) return dev_fail(e, "hydro_sweep");
+  p->acc_valid = true;
+  if (dt)
+    for (int i = 0; i < p->n; ++i) dt[i] = s[i].dt;
   return HYDRO_OK;
 }
 
-int hydro_step(hydro_t* h) {
-  int rc = check_bound(h);
+int do_step(hydro::Plan* p) {
+  int rc = check_bound(p);
   if (rc) return rc;
-  DeviceGuard g(h->device);
-  hipError_t e = hipSuccess;
-  if (!h->acc_valid) {
-    PhaseTimer pt(h, HYDRO_PHASE_DT);
-    e = h->dtype == HYDRO_F64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
-  }
-  if (e == hipSuccess) e = enqueue_step_body(h);
+  DeviceGuard g(p->device);
+  hipError_t e = p->enqueue_step();
   if (e != hipSuccess) {
-    h->acc_valid = false;
-    return dev_fail(e, "hydro_step");
+    p->acc_valid = false;
+    return dev_fail(e, "step");
   }
-  h->acc_valid = true;
   return HYDRO_OK;
 }
 
-int hydro_graph_steps(hydro_t* h, int nsteps) {
-  int rc = check_bound(h);
+int do_graph_steps(hydro::Plan* p, int nsteps) {
+  int rc = check_bound(p);
   if (rc) return rc;
   if (nsteps < 1 || nsteps > 4096) return fail(HYDRO_EINVAL, "nsteps %d: 1..4096", nsteps);
-  if (h->stream == nullptr)
-    return fail(HYDRO_ESTATE, "graph capture needs a non-default stream (hydro_bind)");
-  DeviceGuard g(h->device);
-  hipError_t e = hipSuccess;
-  if (!h->acc_valid) {
-    // the graph starts from a valid max speed; compute it eagerly once
-    e = h->dtype == HYDRO_F64 ? enqueue_max_speed<double>(h) : enqueue_max_speed<float>(h);
-    if (e != hipSuccess) return dev_fail(e, "hydro_graph_steps");
-    h->acc_valid = true;
-  }
-  if (!h->gexec || h->graph_steps != nsteps) {
-    drop_graph(h);
-    const bool prof = h->profiling;
-    h->profiling = false;
-    e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
-    for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = enqueue_step_body(h);
-    hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
-    h->profiling = prof;
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      h->gexec = nullptr;
-      return dev_fail(e, "graph capture");
-    }
-    h->graph_steps = nsteps;
-  }
-  e = hipGraphLaunch(h->gexec, h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hipGraphLaunch");
+  if (p->stream == nullptr)
+    return fail(HYDRO_ESTATE, "graph capture needs a non-default stream (bind)");
+  DeviceGuard g(p->device);
+  hipError_t e = p->graph_launch(nsteps);
+  if (e != hipSuccess) return dev_fail(e, "graph steps");
   return HYDRO_OK;
 }
 
-int hydro_conserved_totals(hydro_t* h, double out[4]) {
-  int rc = check_bound(h);
+int do_totals(hydro::Plan* p, double* out) {
+  int rc = check_bound(p);
   if (rc) return rc;
   if (!out) return fail(HYDRO_EINVAL, "NULL output");
-  DeviceGuard g(h->device);
-  hipError_t e = h->dtype == HYDRO_F64 ? enqueue_totals<double>(h) : enqueue_totals<float>(h);
-  if (e != hipSuccess) return dev_fail(e, "hydro_conserved_totals");
-  DevState s;
-  rc = sync_state(h, &s);
+  DeviceGuard g(p->device);
+  hipError_t e = p->enqueue_totals();
+  if (e != hipSuccess) return dev_fail(e, "totals");
+  std::vector<hydro::DevState> s;
+  rc = sync_states(p, s);
   if (rc) return rc;
-  for (int k = 0; k < 4; ++k) out[k] = s.totals[k];
+  for (int i = 0; i < p->n; ++i)
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = s[i].totals[k];
   return HYDRO_OK;
 }
 
-int hydro_get_clock(hydro_t* h, double* t, long* step, double* dt) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  DeviceGuard g(h->device);
-  DevState s;
-  hipError_t e = hipMemcpyAsync(&s, h->st, sizeof s, hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hydro_get_clock");
-  if (t) *t = s.t;
-  if (step) *step = (long)s.step;
-  if (dt) *dt = s.dt;
+int do_get_clock(hydro::Plan* p, double* t, long* step, double* dt) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  DeviceGuard g(p->device);
+  std::vector<hydro::DevState> s;
+  hipError_t e = p->sync_states(s);
+  if (e != hipSuccess) return dev_fail(e, "get_clock");
+  for (int i = 0; i < p->n; ++i) {
+    if (t) t[i] = s[i].t;
+    if (step) step[i] = (long)s[i].step;
+    if (dt) dt[i] = s[i].dt;
+  }
   return HYDRO_OK;
 }
 
-int hydro_set_clock(hydro_t* h, double t, long step) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  if (!std::isfinite(t) || step < 0) return fail(HYDRO_EINVAL, "clock t=%g step=%ld", t, step);
-  DeviceGuard g(h->device);
-  hipError_t e = hydro::launch_set_clock(h->st, t, step, h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hydro_set_clock");
-  return HYDRO_OK;
-}
-
-int hydro_riemann_stats(hydro_t* h, hydro_stats_t* out, int reset) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  DeviceGuard g(h->device);
-  DevState s;
-  hipError_t e = hipMemcpyAsync(&s, h->st, sizeof s, hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return dev_fail(e, "hydro_riemann_stats");
+int do_stats(hydro::Plan* p, hydro_stats_t* out, int reset) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  DeviceGuard g(p->device);
+  std::vector<hydro::DevState> s;
+  hipError_t e = p->sync_states(s);
+  if (e != hipSuccess) return dev_fail(e, "riemann_stats");
   if (out) {
     std::memset(out, 0, sizeof *out);
-    out->interfaces = (long long)s.interfaces;
-    for (int k = 0; k <= HYDRO_MAX_NITER; ++k) out->hist[k] = (long long)s.hist[k];
-    out->fallbacks = (long long)s.fallbacks;
+    for (int i = 0; i < p->n; ++i) {
+      out->interfaces += (long long)s[i].interfaces;
+      for (int k = 0; k <= HYDRO_MAX_NITER; ++k) out->hist[k] += (long long)s[i].hist[k];
+      out->fallbacks += (long long)s[i].fallbacks;
+    }
   }
   if (reset) {
-    e = hydro::launch_clear_stats(h->st, h->stream);
+    e = hydro::launch_clear_stats(p->st, p->n, p->stream);
     if (e != hipSuccess) return dev_fail(e, "stats reset");
   }
   return HYDRO_OK;
 }
 
-int hydro_set_profiling(hydro_t* h, int enable) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  h->profiling = enable != 0;
+int do_set_options(hydro::Plan* p, const hydro_options_t* o) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  int rc = check_options(o);
+  if (rc) return rc;
+  DeviceGuard g(p->device);
+  hipError_t e = p->set_options(*o);
+  if (e != hipSuccess) return dev_fail(e, "set_options");
   return HYDRO_OK;
 }
 
-int hydro_get_profile(hydro_t* h, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
-                      int reset) {
-  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
-  DeviceGuard g(h->device);
-  if (h->stream || h->bound) {
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return dev_fail(e, "hydro_get_profile");
+int do_autotune(hydro::Plan* p, hydro_tune_t* out, int use_cache) {
+  int rc = check_bound(p);
+  if (rc) return rc;
+  DeviceGuard g(p->device);
+  hipError_t e = p->autotune(out, use_cache != 0);
+  if (e != hipSuccess) return dev_fail(e, "autotune");
+  return HYDRO_OK;
+}
+
+int do_set_profiling(hydro::Plan* p, int enable) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  p->profiling = enable != 0;
+  return HYDRO_OK;
+}
+
+int do_get_profile(hydro::Plan* p, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
+                   int reset) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  DeviceGuard g(p->device);
+  if (p->bound) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return dev_fail(e, "get_profile");
   }
   double acc[HYDRO_NPHASES] = {0, 0, 0};
   long long cnt[HYDRO_NPHASES] = {0, 0, 0};
-  for (const auto& m : h->marks) {
+  for (const auto& m : p->marks) {
     float t = 0.f;
     hipError_t e = hipEventElapsedTime(&t, m.a, m.b);
     if (e != hipSuccess) return dev_fail(e, "hipEventElapsedTime");
@@ -577,13 +263,178 @@ int hydro_get_profile(hydro_t* h, double ms[HYDRO_NPHASES], long long launches[H
     if (launches) launches[k] = cnt[k];
   }
   if (reset) {
-    for (const auto& m : h->marks) {
-      h->ev_pool.push_back(m.a);
-      h->ev_pool.push_back(m.b);
+    for (const auto& m : p->marks) {
+      p->ev_pool.push_back(m.a);
+      p->ev_pool.push_back(m.b);
     }
-    h->marks.clear();
+    p->marks.clear();
   }
   return HYDRO_OK;
+}
+
+int check_state_ptr(const hydro::Plan* p, void* U, int dtype) {
+  if (!U) return fail(HYDRO_EINVAL, "NULL state pointer");
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return fail(HYDRO_EINVAL, "dtype %d", dtype);
+  const size_t elem = dtype == HYDRO_F64 ? 8 : 4;
+  if (((uintptr_t)U) % elem != 0) return fail(HYDRO_EINVAL, "state pointer misaligned");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, U) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(HYDRO_EINVAL, "state pointer is not device memory");
+  }
+  if (attr.device != p->device)
+    return fail(HYDRO_EINVAL, "state on device %d, handle on device %d", attr.device, p->device);
+  return HYDRO_OK;
+}
+
+int do_bind(hydro::Plan* p, void* U, const long* pitches, const long long* offsets, int dtype,
+            void* stream) {
+  DeviceGuard g(p->device);
+  hipError_t e = p->bind(U, pitches, offsets, dtype, (hipStream_t)stream);
+  if (e == hipErrorOutOfMemory) return fail(HYDRO_ENOMEM, "second state buffer: out of memory");
+  if (e != hipSuccess) return dev_fail(e, "bind");
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hydro_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------ single grid
+hydro_t* hydro_create(int nx, int ny, double gamma, double cfl, int bc) {
+  return create_plan<hydro_s>(1, &nx, &ny, gamma, cfl, &bc);
+}
+
+void hydro_destroy(hydro_t* h) { delete h; }
+
+int hydro_bind(hydro_t* h, void* U, long pitch, int dtype, void* hip_stream) {
+  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
+  int rc = check_state_ptr(h, U, dtype);
+  if (rc) return rc;
+  if (pitch < h->nx[0]) return fail(HYDRO_EINVAL, "pitch %ld < nx %d", pitch, h->nx[0]);
+  if (pitch > (1l << 30)) return fail(HYDRO_EINVAL, "pitch %ld too large", pitch);
+  const long long off = 0;
+  return do_bind(h, U, &pitch, &off, dtype, hip_stream);
+}
+
+int hydro_invalidate(hydro_t* h) {
+  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
+  h->acc_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_set_options(hydro_t* h, const hydro_options_t* o) { return do_set_options(h, o); }
+
+int hydro_get_options(const hydro_t* h, hydro_options_t* o) {
+  if (!h || !o) return fail(HYDRO_EINVAL, "NULL argument");
+  *o = h->opt;
+  return HYDRO_OK;
+}
+
+double hydro_compute_dt(hydro_t* h) {
+  double dt = 0.0;
+  int rc = do_compute_dt(h, &dt);
+  return rc ? (double)rc : dt;
+}
+
+int hydro_sweep(hydro_t* h, int dir) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (dir != HYDRO_DIR_X && dir != HYDRO_DIR_Y) return fail(HYDRO_EINVAL, "dir %d", dir);
+  DeviceGuard g(h->device);
+  hipError_t e = h->enqueue_single_sweep(dir);
+  if (e != hipSuccess) return dev_fail(e, "hydro_sweep");
+  return HYDRO_OK;
+}
+
+int hydro_step(hydro_t* h) { return do_step(h); }
+int hydro_graph_steps(hydro_t* h, int nsteps) { return do_graph_steps(h, nsteps); }
+int hydro_conserved_totals(hydro_t* h, double out[4]) { return do_totals(h, out); }
+
+int hydro_get_clock(hydro_t* h, double* t, long* step, double* dt) {
+  return do_get_clock(h, t, step, dt);
+}
+
+int hydro_set_clock(hydro_t* h, double t, long step) {
+  if (!h) return fail(HYDRO_EINVAL, "NULL handle");
+  if (!std::isfinite(t) || step < 0) return fail(HYDRO_EINVAL, "clock t=%g step=%ld", t, step);
+  DeviceGuard g(h->device);
+  hipError_t e = hydro::launch_set_clock(h->st, 0, t, step, h->stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_set_clock");
+  return HYDRO_OK;
+}
+
+int hydro_riemann_stats(hydro_t* h, hydro_stats_t* s, int reset) { return do_stats(h, s, reset); }
+int hydro_autotune(hydro_t* h, hydro_tune_t* out, int use_cache) {
+  return do_autotune(h, out, use_cache);
+}
+int hydro_set_profiling(hydro_t* h, int enable) { return do_set_profiling(h, enable); }
+int hydro_get_profile(hydro_t* h, double ms[HYDRO_NPHASES], long long launches[HYDRO_NPHASES],
+                      int reset) {
+  return do_get_profile(h, ms, launches, reset);
+}
+
+// ------------------------------------------------------------ batches
+hydro_batch_t* hydro_batch_create(int n, const int* nx, const int* ny, double gamma, double cfl,
+                                  const int* bc) {
+  return create_plan<hydro_batch_s>(n, nx, ny, gamma, cfl, bc);
+}
+
+void hydro_batch_destroy(hydro_batch_t* b) { delete b; }
+
+long long hydro_batch_layout(const hydro_batch_t* b, int dtype, long long* offsets,
+                             long* pitches) {
+  if (!b) return fail(HYDRO_EINVAL, "NULL handle");
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return fail(HYDRO_EINVAL, "dtype %d", dtype);
+  long long total = 0;
+  for (int g = 0; g < b->n; ++g) {
+    const long p = hydro::padded_pitch(b->nx[g], dtype);
+    if (offsets) offsets[g] = total;
+    if (pitches) pitches[g] = p;
+    total += 4LL * p * b->ny[g];
+  }
+  return total;
+}
+
+int hydro_batch_bind(hydro_batch_t* b, void* U, int dtype, void* hip_stream) {
+  if (!b) return fail(HYDRO_EINVAL, "NULL handle");
+  int rc = check_state_ptr(b, U, dtype);
+  if (rc) return rc;
+  std::vector<long long> off(b->n);
+  std::vector<long> pitch(b->n);
+  hydro_batch_layout(b, dtype, off.data(), pitch.data());
+  return do_bind(b, U, pitch.data(), off.data(), dtype, hip_stream);
+}
+
+int hydro_batch_set_options(hydro_batch_t* b, const hydro_options_t* o) {
+  return do_set_options(b, o);
+}
+
+int hydro_batch_invalidate(hydro_batch_t* b) {
+  if (!b) return fail(HYDRO_EINVAL, "NULL handle");
+  b->acc_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_batch_compute_dt(hydro_batch_t* b, double* dt) { return do_compute_dt(b, dt); }
+int hydro_batch_step(hydro_batch_t* b) { return do_step(b); }
+int hydro_batch_graph_steps(hydro_batch_t* b, int nsteps) { return do_graph_steps(b, nsteps); }
+int hydro_batch_totals(hydro_batch_t* b, double* out) { return do_totals(b, out); }
+int hydro_batch_get_clock(hydro_batch_t* b, double* t, long* step, double* dt) {
+  return do_get_clock(b, t, step, dt);
+}
+int hydro_batch_riemann_stats(hydro_batch_t* b, hydro_stats_t* s, int reset) {
+  return do_stats(b, s, reset);
+}
+int hydro_batch_autotune(hydro_batch_t* b, hydro_tune_t* out, int use_cache) {
+  return do_autotune(b, out, use_cache);
+}
+int hydro_batch_set_profiling(hydro_batch_t* b, int enable) { return do_set_profiling(b, enable); }
+int hydro_batch_get_profile(hydro_batch_t* b, double ms[HYDRO_NPHASES],
+                            long long launches[HYDRO_NPHASES], int reset) {
+  return do_get_profile(b, ms, launches, reset);
 }
 
 }  // extern "C"

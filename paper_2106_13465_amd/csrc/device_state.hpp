@@ -1,7 +1,13 @@
 // device_state.hpp -- plain structs shared by the kernels and the host side of
-// the library: the per-grid kernel arguments and the small device-resident
-// scratch of a handle (time step, clock, max-speed accumulator, status word,
-// Riemann statistics, totals).
+// the library: per-grid device scratch (time step, clock, max-speed
+// accumulator, status word, Riemann statistics, totals), per-grid geometry and
+// the kernel argument that describes a batch of grids.
+//
+// Every launch works on a batch: a single grid is a batch of one.  Grid g's
+// state lives at offset GridDesc::off of two equally laid-out buffers; its
+// variable plane v of cell (x, y) is at off + v * plane + y * pitch + x.  A
+// sweep reads one buffer and writes the other, so no wave ever reads a cell
+// another wave has already updated.
 #pragma once
 #include <stdint.h>
 
@@ -12,6 +18,8 @@ namespace hydro {
 constexpr int kMaxIter = 32;      // largest Newton cap (HYDRO_MAX_NITER)
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kXOut = kWave - 4;  // x-sweep cells updated per 64-lane segment
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxTotBlocks = 512;  // partial-sum blocks per grid for totals
 
 // status word bits
 constexpr int kStatusNonPhys = 1;
@@ -30,19 +38,29 @@ struct DevState {
   unsigned long long fallbacks;
 };
 
-// One grid of the state: plane v of cell (x, y) at U[v * plane + y * pitch + x].
-// A sweep reads src and writes dst (distinct buffers of the same layout), so
-// no wave ever reads a cell another wave has already updated.
+struct GridDesc {
+  long long off;    // element offset of plane 0 in the state buffers
+  long long plane;  // elements per variable plane (ny * pitch)
+  int pitch, nx, ny, bc;
+  double h;         // cell size 1/max(nx, ny)
+  double cfl;
+  long long wx0;    // first global wave of this grid in the x-sweep
+  long long wy0;    // first global wave of this grid in the y-sweep
+  long long r0;     // first global row (row-item kernels)
+  int tb0;          // first partial block of the totals
+  int ntb;          // partial blocks of the totals
+};
+
+// Kernel argument of one launch over a batch.
 template <typename T>
-struct GridArgs {
+struct Batch {
   const T* src;
   T* dst;
-  long long plane;
-  int pitch;
-  int nx, ny;
-  int bc;
-  double h;    // cell size
-  double cfl;
+  const GridDesc* g;  // device array [ngrids]
+  DevState* st;       // device array [ngrids]
+  int ngrids;
+  int seg;            // x-sweep: 60-cell segments per wave item; y-sweep: rows per item
+  long long items;    // waves (sweeps) or rows (row kernels) over the whole batch
 };
 
 }  // namespace hydro

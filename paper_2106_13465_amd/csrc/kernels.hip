@@ -1,4 +1,11 @@
-// kernels.hip -- gfx950 kernels of the split Godunov sweep and its time step.
+// kernels.hip -- gfx950 kernels of the split Godunov sweep and its time step,
+// all working on a batch of grids (a single grid is a batch of one).
+//
+// Work items are waves.  A launch covers the whole batch: the global wave
+// index is mapped to (grid, local item) by a binary search over the grids'
+// first-item prefix table (wave-uniform, scalar loads).  Launches are
+// persistent when the launcher passes fewer blocks than items: each wave then
+// strides over the items.
 //
 // x-sweep (rows, the contiguous direction): one lane per cell.  A 64-lane
 //   wave holds cells x0-2 .. x0+61 of one row, loaded coalesced with the
@@ -6,15 +13,16 @@
 //   cross-lane shuffles (primitive variables for the slopes, left face states
 //   for the Riemann problems, fluxes for the update), and lanes 2..61 write
 //   the 60 updated cells.  Every interface a wave needs is solved by its own
-//   lane, so there is no divergent halo pass.
+//   lane, so there is no divergent halo pass.  An item is `seg` consecutive
+//   60-cell segments of one row.
 // y-sweep (columns): one thread per column marches down a segment of rows
 //   with a register window of the 5-cell stencil (paper, Figure 2); lanes
 //   run along x, so every load and store of the wave is one coalesced row
 //   access without an LDS transpose.  The epilogue computes the max wave
-//   speed of the new state for the next step's dt (fused CFL reduction).
+//   speed of the new state for the grid's next dt (fused CFL reduction).
 //
-// Both read the stored dt from device memory, so a step launches without a
-// host round trip and can be captured into a HIP graph.
+// Both read the grid's stored dt from device memory, so a step launches
+// without a host round trip and can be captured into a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include "device_state.hpp"
@@ -76,82 +84,110 @@ __device__ __forceinline__ bool nonphysical(T r, T e) {
   return !(r > T(0)) || !(fabs(e) < T(INFINITY));
 }
 
-template <typename T>
-__device__ __forceinline__ T step_lambda(const DevState* st, double h) {
-  return T(st->dt / h);
+// First work item of this wave and the stride between a wave's items; both
+// wave-uniform.
+__device__ __forceinline__ long long first_wave() {
+  const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  return (long long)blockIdx.x * kWavesPerBlock + wib;
+}
+__device__ __forceinline__ long long wave_stride() {
+  return (long long)gridDim.x * kWavesPerBlock;
+}
+
+// Last grid whose first item is <= w (prefix tables start at 0 and never
+// decrease).
+enum class Key { X, Y, Row };
+template <Key K>
+__device__ __forceinline__ long long key_of(const GridDesc& d) {
+  return K == Key::X ? d.wx0 : (K == Key::Y ? d.wy0 : d.r0);
+}
+template <Key K>
+__device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key_of<K>(g[mid]) <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 // ------------------------------------------------------------ x-sweep
 template <typename T, bool STATS>
-__global__ __launch_bounds__(256) void k_sweep_x(GridArgs<T> a, Gas<T> G, DevState* st,
-                                                 int segs_per_wave) {
+__global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G) {
   const int lane = threadIdx.x & (kWave - 1);
-  const long long wave = (long long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int nseg = (a.nx + kXOut - 1) / kXOut;
-  const int chunks = (nseg + segs_per_wave - 1) / segs_per_wave;
-  if (wave >= (long long)chunks * a.ny) return;
-  const int row = (int)(wave / chunks);
-  const int seg0 = (int)(wave % chunks) * segs_per_wave;
-  const T lam = step_lambda<T>(st, a.h);
-  const T* rowp = a.src + (long long)row * a.pitch;
-  T* outp = a.dst + (long long)row * a.pitch;
-  const long long P = a.plane;
-  int status = 0;
+  for (long long w = first_wave(); w < b.items; w += wave_stride()) {
+    const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
+    const GridDesc d = b.g[gi];
+    DevState* st = b.st + gi;
+    const int lw = (int)(w - d.wx0);
+    const int nseg = (d.nx + kXOut - 1) / kXOut;
+    const int chunks = (nseg + b.seg - 1) / b.seg;
+    const int row = lw / chunks;
+    const int seg0 = (lw - row * chunks) * b.seg;
+    const T lam = T(st->dt / d.h);
+    const T* rowp = b.src + d.off + (long long)row * d.pitch;
+    T* outp = b.dst + d.off + (long long)row * d.pitch;
+    const long long P = d.plane;
+    int status = 0;
 
-  for (int sgi = 0; sgi < segs_per_wave; ++sgi) {
-    const int seg = seg0 + sgi;
-    if (seg >= nseg) break;
-    const int x0 = seg * kXOut;
-    const int i = x0 - 2 + lane;  // cell of this lane, in [-2, nx+1] when used
-    bool flip;
-    const int src = ghost_source(min(i, a.nx + 1), a.nx, a.bc, flip);
-    T u0 = rowp[src];
-    T un = rowp[P + src];
-    T ut = rowp[2 * P + src];
-    T e = rowp[3 * P + src];
-    if (flip) un = -un;
+    for (int sgi = 0; sgi < b.seg; ++sgi) {
+      const int seg = seg0 + sgi;
+      if (seg >= nseg) break;
+      const int x0 = seg * kXOut;
+      const int i = x0 - 2 + lane;  // cell of this lane, in [-2, nx+1] when used
+      bool flip;
+      const int src = ghost_source(min(i, d.nx + 1), d.nx, d.bc, flip);
+      T u0 = rowp[src];
+      T un = rowp[P + src];
+      T ut = rowp[2 * P + src];
+      T e = rowp[3 * P + src];
+      if (flip) un = -un;
 
-    // COMPUTE: primitive variables, slopes, half-step face states
-    T ir;
-    const Prim<T> q = cons_to_prim(u0, un, ut, e, G, ir);
-    const Prim<T> ql = from_left(q);
-    const Prim<T> qr = from_right(q);
-    Prim<T> d;
-    d.r = minmod(q.r - ql.r, qr.r - q.r);
-    d.u = minmod(q.u - ql.u, qr.u - q.u);
-    d.t = minmod(q.t - ql.t, qr.t - q.t);
-    d.p = minmod(q.p - ql.p, qr.p - q.p);
-    Prim<T> qm, qp;
-    trace(q, ir, d, lam, G, qm, qp);
+      // COMPUTE: primitive variables, slopes, half-step face states
+      T ir;
+      const Prim<T> q = cons_to_prim(u0, un, ut, e, G, ir);
+      const Prim<T> ql = from_left(q);
+      const Prim<T> qr = from_right(q);
+      Prim<T> dq;
+      dq.r = minmod(q.r - ql.r, qr.r - q.r);
+      dq.u = minmod(q.u - ql.u, qr.u - q.u);
+      dq.t = minmod(q.t - ql.t, qr.t - q.t);
+      dq.p = minmod(q.p - ql.p, qr.p - q.p);
+      Prim<T> qm, qp;
+      trace(q, ir, dq, lam, G, qm, qp);
 
-    // Riemann problem at this lane's right interface i+1/2
-    const Prim<T> qm_next = from_right(qm);
-    int iters;
-    bool conv;
-    const Flux<T> F = riemann_flux(qp, qm_next, G, iters, conv);
-    const Flux<T> Fl = from_left(F);  // interface i-1/2
+      // Riemann problem at this lane's right interface i+1/2
+      const Prim<T> qm_next = from_right(qm);
+      int iters;
+      bool conv;
+      const Flux<T> F = riemann_flux(qp, qm_next, G, iters, conv);
+      const Flux<T> Fl = from_left(F);  // interface i-1/2
 
-    if (STATS) {
-      // interfaces owned by this segment: x0-1/2 (first segment only) and the
-      // right interfaces of its cells
-      const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < a.nx;
-      count_newton(st, valid, conv ? iters : 0);
+      if (STATS) {
+        // interfaces owned by this segment: x0-1/2 (first segment only) and
+        // the right interfaces of its cells
+        const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
+        count_newton(st, valid, conv ? iters : 0);
+      }
+
+      // WRITE: conservative update of cells x0 .. x0+59
+      if (lane >= 2 && lane < 62 && i < d.nx) {
+        const T nr = u0 + lam * (Fl.m - F.m);
+        const T nn = un + lam * (Fl.n - F.n);
+        const T nt = ut + lam * (Fl.t - F.t);
+        const T ne = e + lam * (Fl.e - F.e);
+        outp[i] = nr;
+        outp[P + i] = nn;
+        outp[2 * P + i] = nt;
+        outp[3 * P + i] = ne;
+        status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+      }
     }
-
-    // WRITE: conservative update of cells x0 .. x0+59
-    if (lane >= 2 && lane < 62 && i < a.nx) {
-      const T nr = u0 + lam * (Fl.m - F.m);
-      const T nn = un + lam * (Fl.n - F.n);
-      const T nt = ut + lam * (Fl.t - F.t);
-      const T ne = e + lam * (Fl.e - F.e);
-      outp[i] = nr;
-      outp[P + i] = nn;
-      outp[2 * P + i] = nt;
-      outp[3 * P + i] = ne;
-      status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-    }
+    if (status) atomicOr(&st->status, status);
   }
-  if (status) atomicOr(&st->status, status);
 }
 
 // ------------------------------------------------------------ y-sweep
@@ -160,147 +196,199 @@ struct Cell {
   T r, n, t, e;  // conservative: density, normal (y) and transverse (x) momentum, energy
 };
 
-template <typename T, bool FUSE_DT, bool STATS>
-__global__ __launch_bounds__(256) void k_sweep_y(GridArgs<T> a, Gas<T> G, DevState* st,
-                                                 int seg) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long wave = (long long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int ncolg = (a.nx + kWave - 1) / kWave;
-  const int nsegs = (a.ny + seg - 1) / seg;
-  if (wave >= (long long)ncolg * nsegs) return;
-  const int cg = (int)(wave % ncolg);
-  const int sg = (int)(wave / ncolg);
-  const int x = cg * kWave + lane;
-  const bool xin = x < a.nx;
-  const T* col = a.src + (xin ? x : a.nx - 1);
-  T* out = a.dst + x;
-  const long long P = a.plane;
-  const int y0 = sg * seg;
-  const int y1 = min(y0 + seg, a.ny);
-  const T lam = step_lambda<T>(st, a.h);
-
-  auto load = [&](int j) {
-    bool flip;
-    const long long off = (long long)ghost_source(j, a.ny, a.bc, flip) * a.pitch;
-    Cell<T> c;
-    c.r = col[off];
-    c.t = col[P + off];      // rho u: transverse
-    c.n = col[2 * P + off];  // rho v: normal
-    c.e = col[3 * P + off];
-    if (flip) c.n = -c.n;
-    return c;
-  };
-  auto slopes = [](const Prim<T>& a_, const Prim<T>& b, const Prim<T>& c) {
-    Prim<T> d;
-    d.r = minmod(b.r - a_.r, c.r - b.r);
-    d.u = minmod(b.u - a_.u, c.u - b.u);
-    d.t = minmod(b.t - a_.t, c.t - b.t);
-    d.p = minmod(b.p - a_.p, c.p - b.p);
-    return d;
-  };
-
-  // One loop body does everything: iteration j READs cell j+2, traces cell
-  // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
-  // four iterations only fill the window (uniform guards), so every step of
-  // the method exists at one code location and an interface shared by two
-  // segments is computed bitwise identically by both.
-  Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
-  Prim<T> q0, q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
-  T ir1, ir2 = T(1);
-  Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
-  Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
-  double smax = 0.0;
-  int status = 0;
-  for (int j = y0 - 4; j < y1; ++j) {
-    c0 = c1;
-    c1 = c2;
-    q0 = q1;
-    q1 = q2;
-    ir1 = ir2;
-    c2 = load(j + 2);
-    q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
-    if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
-    if (j >= y0 - 1) {
-      int iters;
-      bool conv;
-      F = riemann_flux(qp0, qm1, G, iters, conv);
-      if (STATS) count_newton(st, xin && (j >= y0 || y0 == 0), conv ? iters : 0);
-    }
-    if (j >= y0) {
-      const T nr = c0.r + lam * (Fm.m - F.m);
-      const T nn = c0.n + lam * (Fm.n - F.n);
-      const T nt = c0.t + lam * (Fm.t - F.t);
-      const T ne = c0.e + lam * (Fm.e - F.e);
-      if (xin) {
-        const long long off = (long long)j * a.pitch;
-        out[off] = nr;
-        out[P + off] = nt;
-        out[2 * P + off] = nn;
-        out[3 * P + off] = ne;
-        status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-        if (FUSE_DT) smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
-      }
-    }
-    qp0 = qp1;
-    Fm = F;
-  }
-  if (status) atomicOr(&st->status, status);
-  if (FUSE_DT) {
-    smax = wave_max(smax);
-    if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
-  }
-}
-
-// ------------------------------------------------------------ dt
 template <typename T>
-__global__ __launch_bounds__(256) void k_max_speed(GridArgs<T> a, Gas<T> G, DevState* st) {
-  double smax = 0.0;
-  const long long n = (long long)a.nx * a.ny;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int y = (int)(c / a.nx), x = (int)(c % a.nx);
-    const long long off = (long long)y * a.pitch + x;
-    smax = fmax(smax, (double)max_speed(a.src[off], a.src[a.plane + off],
-                                        a.src[2 * a.plane + off], a.src[3 * a.plane + off], G));
+__device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c) {
+  Prim<T> d;
+  d.r = minmod(b.r - a.r, c.r - b.r);
+  d.u = minmod(b.u - a.u, c.u - b.u);
+  d.t = minmod(b.t - a.t, c.t - b.t);
+  d.p = minmod(b.p - a.p, c.p - b.p);
+  return d;
+}
+
+template <typename T, bool FUSE_DT, bool STATS>
+__global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (long long w = first_wave(); w < b.items; w += wave_stride()) {
+    const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
+    const GridDesc d = b.g[gi];
+    DevState* st = b.st + gi;
+    const int lw = (int)(w - d.wy0);
+    const int ncolg = (d.nx + kWave - 1) / kWave;
+    const int sg = lw / ncolg;
+    const int cg = lw - sg * ncolg;
+    const int x = cg * kWave + lane;
+    const bool xin = x < d.nx;
+    const T* col = b.src + d.off + (xin ? x : d.nx - 1);
+    T* out = b.dst + d.off + x;
+    const long long P = d.plane;
+    const int y0 = sg * b.seg;
+    const int y1 = min(y0 + b.seg, d.ny);
+    const T lam = T(st->dt / d.h);
+
+    auto load = [&](int j) {
+      bool flip;
+      const long long off = (long long)ghost_source(j, d.ny, d.bc, flip) * d.pitch;
+      Cell<T> c;
+      c.r = col[off];
+      c.t = col[P + off];      // rho u: transverse
+      c.n = col[2 * P + off];  // rho v: normal
+      c.e = col[3 * P + off];
+      if (flip) c.n = -c.n;
+      return c;
+    };
+
+    // One loop body does everything: iteration j READs cell j+2, traces cell
+    // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
+    // four iterations only fill the window (uniform guards), so every step of
+    // the method exists at one code location and an interface shared by two
+    // segments is computed bitwise identically by both.
+    Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
+    Prim<T> q0, q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
+    T ir1, ir2 = T(1);
+    Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
+    Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
+    double smax = 0.0;
+    int status = 0;
+    for (int j = y0 - 4; j < y1; ++j) {
+      c0 = c1;
+      c1 = c2;
+      q0 = q1;
+      q1 = q2;
+      ir1 = ir2;
+      c2 = load(j + 2);
+      q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
+      if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
+      if (j >= y0 - 1) {
+        int iters;
+        bool conv;
+        F = riemann_flux(qp0, qm1, G, iters, conv);
+        if (STATS) count_newton(st, xin && (j >= y0 || y0 == 0), conv ? iters : 0);
+      }
+      if (j >= y0) {
+        const T nr = c0.r + lam * (Fm.m - F.m);
+        const T nn = c0.n + lam * (Fm.n - F.n);
+        const T nt = c0.t + lam * (Fm.t - F.t);
+        const T ne = c0.e + lam * (Fm.e - F.e);
+        if (xin) {
+          const long long off = (long long)j * d.pitch;
+          out[off] = nr;
+          out[P + off] = nt;
+          out[2 * P + off] = nn;
+          out[3 * P + off] = ne;
+          status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+          if (FUSE_DT) smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
+        }
+      }
+      qp0 = qp1;
+      Fm = F;
+    }
+    if (status) atomicOr(&st->status, status);
+    if (FUSE_DT) {
+      smax = wave_max(smax);
+      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
+    }
   }
-  smax = wave_max(smax);
-  if ((threadIdx.x & (kWave - 1)) == 0)
-    atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
 }
 
-__global__ void k_reset_acc(DevState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->acc = 0ull;
+// ------------------------------------------------------------ row kernels
+// max wave speed of every cell (first step, hydro_compute_dt): one row per item
+template <typename T>
+__global__ __launch_bounds__(256) void k_max_speed(Batch<T> b, Gas<T> G) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (long long w = first_wave(); w < b.items; w += wave_stride()) {
+    const int gi = find_grid<Key::Row>(b.g, b.ngrids, w);
+    const GridDesc d = b.g[gi];
+    const T* rp = b.src + d.off + (w - d.r0) * d.pitch;
+    const long long P = d.plane;
+    double smax = 0.0;
+    for (int x = lane; x < d.nx; x += kWave)
+      smax = fmax(smax, (double)max_speed(rp[x], rp[P + x], rp[2 * P + x], rp[3 * P + x], G));
+    smax = wave_max(smax);
+    if (lane == 0) atomicMax(&b.st[gi].acc, (unsigned long long)__double_as_longlong(smax));
+  }
 }
 
-// dt = cfl h / smax from the accumulated max; optionally advance the clock
-// and clear the accumulator for the next fused reduction.
-__global__ void k_finalize_dt(DevState* st, double cfl, double h, int advance, int reset) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double smax = __longlong_as_double((long long)st->acc);
-  const double dt = cfl * h / smax;
-  st->dt = dt;
-  st->smax = smax;
+// dst <- src over the interior (standalone sweep): one row per item
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(Batch<T> b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (long long w = first_wave(); w < b.items; w += wave_stride()) {
+    const int gi = find_grid<Key::Row>(b.g, b.ngrids, w);
+    const GridDesc d = b.g[gi];
+    const long long base = d.off + (w - d.r0) * d.pitch;
+    for (int x = lane; x < d.nx; x += kWave) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b.dst[base + v * d.plane + x] = b.src[base + v * d.plane + x];
+    }
+  }
+}
+
+// ------------------------------------------------------------ per-grid scalars
+__global__ void k_reset_acc(DevState* st, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) st[i].acc = 0ull;
+}
+
+// dt = cfl h / smax from the grid's accumulated max; optionally advance its
+// clock and clear the accumulator for the next fused reduction.
+__global__ void k_finalize_dt(const GridDesc* g, DevState* st, int n, int advance, int reset) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DevState& s = st[i];
+  const double smax = __longlong_as_double((long long)s.acc);
+  const double dt = g[i].cfl * g[i].h / smax;
+  s.dt = dt;
+  s.smax = smax;
   if (advance) {
-    st->t += dt;
-    st->step += 1;
+    s.t += dt;
+    s.step += 1;
   }
-  if (reset) st->acc = 0ull;
+  if (reset) s.acc = 0ull;
+}
+
+__global__ void k_set_clock(DevState* st, int i, double t, long long step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[i].t = t;
+    st[i].step = step;
+  }
+}
+
+__global__ void k_clear_stats(DevState* st, int n) {
+  const int gi = blockIdx.x;
+  const int i = threadIdx.x;
+  if (gi >= n) return;
+  if (i <= kMaxIter) st[gi].hist[i] = 0ull;
+  if (i == 0) {
+    st[gi].interfaces = 0ull;
+    st[gi].fallbacks = 0ull;
+  }
 }
 
 // ------------------------------------------------------------ totals
-constexpr int kTotBlocks = 512;
-
-// Block b sums rows b, b+kTotBlocks, ...; each thread a fixed strided set of
-// cells; then a fixed-shape tree.  The result does not depend on scheduling.
+// Grid g owns partial blocks tb0 .. tb0+ntb-1; block k of a grid sums rows
+// k, k+ntb, ... with each thread a fixed strided set of cells, then a
+// fixed-shape tree.  The final kernel (one block per grid) adds the grid's
+// partials in a fixed order.  Results do not depend on scheduling.
 template <typename T>
-__global__ __launch_bounds__(256) void k_totals(GridArgs<T> a, double* partials) {
+__global__ __launch_bounds__(256) void k_totals(Batch<T> b, double* partials) {
   __shared__ double sh[4][256];
+  int lo = 0, hi = b.ngrids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.g[mid].tb0 <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GridDesc d = b.g[lo];
+  const int k = blockIdx.x - d.tb0;
   double s[4] = {0, 0, 0, 0};
-  for (int y = blockIdx.x; y < a.ny; y += gridDim.x) {
-    const T* rowp = a.src + (long long)y * a.pitch;
-    for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+  for (int y = k; y < d.ny; y += d.ntb) {
+    const T* rowp = b.src + d.off + (long long)y * d.pitch;
+    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) s[v] += (double)rowp[v * a.plane + x];
+      for (int v = 0; v < 4; ++v) s[v] += (double)rowp[v * d.plane + x];
     }
   }
 #pragma unroll
@@ -316,13 +404,14 @@ __global__ __launch_bounds__(256) void k_totals(GridArgs<T> a, double* partials)
   if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(256) void k_totals_final(const double* partials, int nb, double h,
+__global__ __launch_bounds__(256) void k_totals_final(const GridDesc* g, const double* partials,
                                                       DevState* st) {
   __shared__ double sh[4][256];
+  const GridDesc d = g[blockIdx.x];
   double s[4] = {0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+  for (int k = threadIdx.x; k < d.ntb; k += blockDim.x) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) s[v] += partials[b * 4 + v];
+    for (int v = 0; v < 4; ++v) s[v] += partials[(d.tb0 + k) * 4 + v];
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
@@ -334,133 +423,97 @@ __global__ __launch_bounds__(256) void k_totals_final(const double* partials, in
     }
     __syncthreads();
   }
-  if (threadIdx.x < 4) st->totals[threadIdx.x] = sh[threadIdx.x][0] * (h * h);
-}
-
-// dst <- src over the nx x ny interior of all four planes
-template <typename T>
-__global__ __launch_bounds__(256) void k_copy(GridArgs<T> a) {
-  const long long n = (long long)a.nx * a.ny;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const long long off = (c / a.nx) * a.pitch + c % a.nx;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a.dst[v * a.plane + off] = a.src[v * a.plane + off];
-  }
-}
-
-__global__ void k_set_clock(DevState* st, double t, long long step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->t = t;
-    st->step = step;
-  }
-}
-
-__global__ void k_clear_stats(DevState* st) {
-  const int i = threadIdx.x;
-  if (i <= kMaxIter) st->hist[i] = 0ull;
-  if (i == 0) {
-    st->interfaces = 0ull;
-    st->fallbacks = 0ull;
-  }
+  if (threadIdx.x < 4) st[blockIdx.x].totals[threadIdx.x] = sh[threadIdx.x][0] * (d.h * d.h);
 }
 
 // ------------------------------------------------------------ launchers
-static inline unsigned blocks_for(long long waves, int waves_per_block) {
-  return (unsigned)((waves + waves_per_block - 1) / waves_per_block);
+static inline unsigned blocks_for(long long items, unsigned max_blocks) {
+  long long nb = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (max_blocks > 0 && nb > (long long)max_blocks) nb = max_blocks;
+  return (unsigned)(nb > 0 ? nb : 1);
 }
 
 template <typename T>
-hipError_t launch_sweep_x(const GridArgs<T>& a, const Gas<T>& G, DevState* st, int segs,
-                          bool stats, hipStream_t s) {
-  const int nseg = (a.nx + kXOut - 1) / kXOut;
-  const long long waves = (long long)((nseg + segs - 1) / segs) * a.ny;
-  const dim3 grid(blocks_for(waves, 4)), block(256);
+hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, bool stats, unsigned max_blocks,
+                          hipStream_t s) {
+  const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
   if (stats)
-    hipLaunchKernelGGL((k_sweep_x<T, true>), grid, block, 0, s, a, G, st, segs);
+    hipLaunchKernelGGL((k_sweep_x<T, true>), grid, block, 0, s, b, G);
   else
-    hipLaunchKernelGGL((k_sweep_x<T, false>), grid, block, 0, s, a, G, st, segs);
+    hipLaunchKernelGGL((k_sweep_x<T, false>), grid, block, 0, s, b, G);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sweep_y(const GridArgs<T>& a, const Gas<T>& G, DevState* st, int seg,
-                          bool fuse_dt, bool stats, hipStream_t s) {
-  const long long waves = (long long)((a.nx + kWave - 1) / kWave) * ((a.ny + seg - 1) / seg);
-  const dim3 grid(blocks_for(waves, 4)), block(256);
+hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, bool fuse_dt, bool stats,
+                          unsigned max_blocks, hipStream_t s) {
+  const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
   if (fuse_dt) {
     if (stats)
-      hipLaunchKernelGGL((k_sweep_y<T, true, true>), grid, block, 0, s, a, G, st, seg);
+      hipLaunchKernelGGL((k_sweep_y<T, true, true>), grid, block, 0, s, b, G);
     else
-      hipLaunchKernelGGL((k_sweep_y<T, true, false>), grid, block, 0, s, a, G, st, seg);
+      hipLaunchKernelGGL((k_sweep_y<T, true, false>), grid, block, 0, s, b, G);
   } else {
     if (stats)
-      hipLaunchKernelGGL((k_sweep_y<T, false, true>), grid, block, 0, s, a, G, st, seg);
+      hipLaunchKernelGGL((k_sweep_y<T, false, true>), grid, block, 0, s, b, G);
     else
-      hipLaunchKernelGGL((k_sweep_y<T, false, false>), grid, block, 0, s, a, G, st, seg);
+      hipLaunchKernelGGL((k_sweep_y<T, false, false>), grid, block, 0, s, b, G);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_max_speed(const GridArgs<T>& a, const Gas<T>& G, DevState* st, hipStream_t s) {
-  const long long n = (long long)a.nx * a.ny;
-  unsigned nb = (unsigned)((n + 255) / 256);
-  if (nb > 4096) nb = 4096;
-  hipLaunchKernelGGL((k_max_speed<T>), dim3(nb), dim3(256), 0, s, a, G, st);
+hipError_t launch_max_speed(const Batch<T>& b, const Gas<T>& G, hipStream_t s) {
+  hipLaunchKernelGGL((k_max_speed<T>), dim3(blocks_for(b.items, 4096)),
+                     dim3(kWave * kWavesPerBlock), 0, s, b, G);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_copy(const GridArgs<T>& a, hipStream_t s) {
-  const long long n = (long long)a.nx * a.ny;
-  unsigned nb = (unsigned)((n + 255) / 256);
-  if (nb > 8192) nb = 8192;
-  hipLaunchKernelGGL((k_copy<T>), dim3(nb), dim3(256), 0, s, a);
+hipError_t launch_copy(const Batch<T>& b, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<T>), dim3(blocks_for(b.items, 8192)), dim3(kWave * kWavesPerBlock),
+                     0, s, b);
   return hipGetLastError();
 }
 
-hipError_t launch_reset_acc(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_acc, dim3(1), dim3(64), 0, s, st);
+template <typename T>
+hipError_t launch_totals(const Batch<T>& b, int total_blocks, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_totals<T>), dim3(total_blocks), dim3(256), 0, s, b, partials);
+  hipLaunchKernelGGL(k_totals_final, dim3(b.ngrids), dim3(256), 0, s, b.g,
+                     (const double*)partials, b.st);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_dt(DevState* st, double cfl, double h, bool advance, bool reset,
+hipError_t launch_reset_acc(DevState* st, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_acc, dim3((n + 255) / 256), dim3(256), 0, s, st, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_dt(const GridDesc* g, DevState* st, int n, bool advance, bool reset,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_dt, dim3(1), dim3(64), 0, s, st, cfl, h, advance ? 1 : 0,
-                     reset ? 1 : 0);
+  hipLaunchKernelGGL(k_finalize_dt, dim3((n + 255) / 256), dim3(256), 0, s, g, st, n,
+                     advance ? 1 : 0, reset ? 1 : 0);
   return hipGetLastError();
 }
 
-int totals_blocks() { return kTotBlocks; }
-
-template <typename T>
-hipError_t launch_totals(const GridArgs<T>& a, double* partials, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_totals<T>), dim3(kTotBlocks), dim3(256), 0, s, a, partials);
-  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, s, (const double*)partials,
-                     kTotBlocks, a.h, st);
+hipError_t launch_set_clock(DevState* st, int i, double t, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, st, i, t, step);
   return hipGetLastError();
 }
 
-hipError_t launch_set_clock(DevState* st, double t, long long step, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, st, t, step);
+hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_stats, dim3(n), dim3(64), 0, s, st, n);
   return hipGetLastError();
 }
 
-hipError_t launch_clear_stats(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_stats, dim3(1), dim3(64), 0, s, st);
-  return hipGetLastError();
-}
-
-#define HYDRO_INSTANTIATE(T)                                                                 \
-  template hipError_t launch_sweep_x<T>(const GridArgs<T>&, const Gas<T>&, DevState*, int,  \
-                                        bool, hipStream_t);                                 \
-  template hipError_t launch_sweep_y<T>(const GridArgs<T>&, const Gas<T>&, DevState*, int,  \
-                                        bool, bool, hipStream_t);                           \
-  template hipError_t launch_max_speed<T>(const GridArgs<T>&, const Gas<T>&, DevState*,     \
-                                          hipStream_t);                                     \
-  template hipError_t launch_totals<T>(const GridArgs<T>&, double*, DevState*, hipStream_t); \
-  template hipError_t launch_copy<T>(const GridArgs<T>&, hipStream_t);
+#define HYDRO_INSTANTIATE(T)                                                                   \
+  template hipError_t launch_sweep_x<T>(const Batch<T>&, const Gas<T>&, bool, unsigned,       \
+                                        hipStream_t);                                         \
+  template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, bool, bool, unsigned, \
+                                        hipStream_t);                                         \
+  template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
+  template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
+  template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);
 
 HYDRO_INSTANTIATE(double)
 HYDRO_INSTANTIATE(float)

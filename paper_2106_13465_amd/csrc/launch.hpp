@@ -1,5 +1,7 @@
-// launch.hpp -- host-side launchers of the sweep, dt and totals kernels.
-// All enqueue on the given stream and return the launch status.
+// launch.hpp -- host-side launchers of the batch kernels.  All enqueue on the
+// given stream and return the launch status.  max_blocks = 0 launches one
+// block per four work items; a smaller positive value makes the sweep
+// persistent (each wave strides over items).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,24 +10,22 @@
 namespace hydro {
 
 template <typename T>
-hipError_t launch_sweep_x(const GridArgs<T>& a, const Gas<T>& G, DevState* st, int segs,
-                          bool stats, hipStream_t s);
+hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, bool stats, unsigned max_blocks,
+                          hipStream_t s);
 template <typename T>
-hipError_t launch_sweep_y(const GridArgs<T>& a, const Gas<T>& G, DevState* st, int seg,
-                          bool fuse_dt, bool stats, hipStream_t s);
+hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, bool fuse_dt, bool stats,
+                          unsigned max_blocks, hipStream_t s);
 template <typename T>
-hipError_t launch_max_speed(const GridArgs<T>& a, const Gas<T>& G, DevState* st, hipStream_t s);
+hipError_t launch_max_speed(const Batch<T>& b, const Gas<T>& G, hipStream_t s);
 template <typename T>
-hipError_t launch_totals(const GridArgs<T>& a, double* partials, DevState* st, hipStream_t s);
+hipError_t launch_copy(const Batch<T>& b, hipStream_t s);
+template <typename T>
+hipError_t launch_totals(const Batch<T>& b, int total_blocks, double* partials, hipStream_t s);
 
-template <typename T>
-hipError_t launch_copy(const GridArgs<T>& a, hipStream_t s);
-
-hipError_t launch_reset_acc(DevState* st, hipStream_t s);
-hipError_t launch_finalize_dt(DevState* st, double cfl, double h, bool advance, bool reset,
+hipError_t launch_reset_acc(DevState* st, int n, hipStream_t s);
+hipError_t launch_finalize_dt(const GridDesc* g, DevState* st, int n, bool advance, bool reset,
                               hipStream_t s);
-hipError_t launch_set_clock(DevState* st, double t, long long step, hipStream_t s);
-hipError_t launch_clear_stats(DevState* st, hipStream_t s);
-int totals_blocks();
+hipError_t launch_set_clock(DevState* st, int i, double t, long long step, hipStream_t s);
+hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s);
 
 }  // namespace hydro

@@ -1,0 +1,447 @@
+// plan.cpp -- host side of a batch of grids (see plan.hpp).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "launch.hpp"
+
+namespace hydro {
+
+namespace {
+
+template <typename T>
+Gas<T> make_gas(double g, const hydro_options_t& o) {
+  Gas<T> G;
+  const double z = (g - 1.0) / (2.0 * g);
+  G.g = T(g);
+  G.gm1 = T(g - 1.0);
+  G.gs = T((g + 1.0) / (2.0 * g));
+  G.z = T(z);
+  G.inv_z = T(1.0 / z);
+  G.half_gm1 = T(0.5 * (g - 1.0));
+  G.h_coef = T(g / (g - 1.0));
+  G.pfloor = T(kCMin * kCMin / g);
+  G.rho_min = T(kRhoMin);
+  G.inv_rho_min = T(1.0 / kRhoMin);
+  G.c_min = T(kCMin);
+  // Convergence can only be detected above the arithmetic's rounding noise:
+  // in FP32 the test is floored at 8 ulp of 1.
+  const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
+  G.tol = T(o.tol > tol_floor ? o.tol : tol_floor);
+  G.niter = o.niter;
+  // 1/z = 2 gamma / (gamma - 1); an integer exponent (7 for gamma = 1.4) lets
+  // the guess use repeated squaring instead of exp2/log2
+  const double k = std::nearbyint(1.0 / z);
+  G.ipow_k = (k >= 1.0 && k <= 64.0 && std::fabs(1.0 / z - k) <= 1e-12 * k) ? (int)k : 0;
+  return G;
+}
+
+template <typename T>
+Batch<T> batch_of(const Plan& p, const void* src, void* dst, int seg, long long items) {
+  Batch<T> b;
+  b.src = static_cast<const T*>(src);
+  b.dst = static_cast<T*>(dst);
+  b.g = p.d_desc;
+  b.st = p.st;
+  b.ngrids = p.n;
+  b.seg = seg;
+  b.items = items;
+  return b;
+}
+
+// Event pair around one phase of a step (no-op unless profiling and the
+// stream is not being captured).
+struct PhaseTimer {
+  Plan* p;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseTimer(Plan* p_, int phase_) : p(p_), phase(phase_) {
+    if (!p->profiling) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, p->stream);
+  }
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!p->ev_pool.empty()) {
+      e = p->ev_pool.back();
+      p->ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  ~PhaseTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, p->stream);
+      p->marks.push_back({phase, a, b});
+    } else {
+      if (a) p->ev_pool.push_back(a);
+      if (b) p->ev_pool.push_back(b);
+    }
+  }
+};
+
+#define HIP_TRY(expr)                     \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return e_;      \
+  } while (0)
+
+}  // namespace
+
+long padded_pitch(int nx, int dtype) {
+  const long per = dtype == HYDRO_F64 ? 32 : 64;  // elements per 256 bytes
+  return (nx + per - 1) / per * per;
+}
+
+Plan::~Plan() {
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (prev != device) (void)hipSetDevice(device);
+  if (bound && stream) (void)hipStreamSynchronize(stream);
+  drop_graph();
+  if (st) (void)hipFree(st);
+  if (d_desc) (void)hipFree(d_desc);
+  if (partials) (void)hipFree(partials);
+  if (V) (void)hipFree(V);
+  for (auto& m : marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
+  if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+}
+
+hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_, double gamma_,
+                      double cfl_) {
+  n = ngrids;
+  nx.assign(nx_, nx_ + n);
+  ny.assign(ny_, ny_ + n);
+  bc.assign(bc_, bc_ + n);
+  gamma = gamma_;
+  cfl = cfl_;
+  std::memset(&opt, 0, sizeof opt);
+  opt.niter = 10;
+  opt.tol = 1e-8;
+  opt.guess = HYDRO_GUESS_PTR;
+  HIP_TRY(hipGetDevice(&device));
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cu > 0)
+    cus = cu;
+  desc.assign(n, GridDesc{});
+  // totals: partial blocks per grid, about 16 rows each, at most kMaxTotBlocks
+  tot_blocks = 0;
+  rows = 0;
+  for (int g = 0; g < n; ++g) {
+    const int nb = std::max(1, std::min(kMaxTotBlocks, (ny[g] + 15) / 16));
+    desc[g].tb0 = tot_blocks;
+    desc[g].ntb = nb;
+    desc[g].r0 = rows;
+    tot_blocks += nb;
+    rows += ny[g];
+    desc[g].nx = nx[g];
+    desc[g].ny = ny[g];
+    desc[g].bc = bc[g];
+    desc[g].h = 1.0 / (double)std::max(nx[g], ny[g]);
+    desc[g].cfl = cfl;
+  }
+  HIP_TRY(hipMalloc((void**)&st, sizeof(DevState) * n));
+  HIP_TRY(hipMalloc((void**)&d_desc, sizeof(GridDesc) * n));
+  HIP_TRY(hipMalloc((void**)&partials, sizeof(double) * 4 * tot_blocks));
+  HIP_TRY(hipMemset(st, 0, sizeof(DevState) * n));
+  return hipDeviceSynchronize();
+}
+
+hipError_t Plan::upload_descriptors() {
+  items_x = 0;
+  items_y = 0;
+  for (int g = 0; g < n; ++g) {
+    GridDesc& d = desc[g];
+    d.off = off.empty() ? 0 : off[g];
+    d.pitch = pitch.empty() ? nx[g] : (int)pitch[g];
+    d.plane = (long long)d.pitch * ny[g];
+    const int nseg = (nx[g] + kXOut - 1) / kXOut;
+    const long long chunks = (nseg + cfg.seg_x - 1) / cfg.seg_x;
+    d.wx0 = items_x;
+    items_x += chunks * ny[g];
+    const long long ncolg = (nx[g] + kWave - 1) / kWave;
+    d.wy0 = items_y;
+    items_y += ncolg * ((ny[g] + cfg.seg_y - 1) / cfg.seg_y);
+  }
+  HIP_TRY(hipMemcpy(d_desc, desc.data(), sizeof(GridDesc) * n, hipMemcpyHostToDevice));
+  drop_graph();
+  return hipSuccess;
+}
+
+hipError_t Plan::bind(void* U_, const long* pitches, const long long* offsets, int dtype_,
+                      hipStream_t s) {
+  pitch.assign(pitches, pitches + n);
+  off.assign(offsets, offsets + n);
+  long long total = 0;
+  for (int g = 0; g < n; ++g) total = std::max(total, off[g] + 4LL * pitch[g] * ny[g]);
+  dtype = dtype_;
+  const size_t bytes = elem_size() * (size_t)total;
+  if (v_bytes != bytes) {
+    if (V) {
+      if (bound && stream) (void)hipStreamSynchronize(stream);
+      (void)hipFree(V);
+      V = nullptr;
+      v_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&V, bytes);
+    if (e != hipSuccess) {
+      V = nullptr;
+      bound = false;
+      return e;
+    }
+    v_bytes = bytes;
+  }
+  elems = total;
+  U = U_;
+  stream = s;
+  bound = true;
+  acc_valid = false;
+  return upload_descriptors();
+}
+
+hipError_t Plan::set_options(const hydro_options_t& o) {
+  opt = o;
+  user_seg_x = o.seg_x > 0;
+  user_seg_y = o.seg_y > 0;
+  if (user_seg_x) cfg.seg_x = o.seg_x;
+  if (user_seg_y) cfg.seg_y = o.seg_y;
+  drop_graph();
+  if (bound) return upload_descriptors();
+  return hipSuccess;
+}
+
+void Plan::drop_graph() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  gexec = nullptr;
+  graph_steps = 0;
+}
+
+hipError_t Plan::enqueue_max_speed() {
+  HIP_TRY(launch_reset_acc(st, n, stream));
+  if (dtype == HYDRO_F64)
+    return launch_max_speed<double>(batch_of<double>(*this, U, nullptr, 0, rows),
+                                    make_gas<double>(gamma, opt), stream);
+  return launch_max_speed<float>(batch_of<float>(*this, U, nullptr, 0, rows),
+                                 make_gas<float>(gamma, opt), stream);
+}
+
+hipError_t Plan::enqueue_finalize(bool advance, bool reset) {
+  return launch_finalize_dt(d_desc, st, n, advance, reset, stream);
+}
+
+hipError_t Plan::enqueue_sweep(int dir, bool fuse_dt, const void* src, void* dst) {
+  const bool stats = opt.stats != 0;
+  if (dtype == HYDRO_F64) {
+    const Gas<double> G = make_gas<double>(gamma, opt);
+    if (dir == HYDRO_DIR_X)
+      return launch_sweep_x<double>(batch_of<double>(*this, src, dst, cfg.seg_x, items_x), G,
+                                    stats, cfg.blocks_x, stream);
+    return launch_sweep_y<double>(batch_of<double>(*this, src, dst, cfg.seg_y, items_y), G,
+                                  fuse_dt, stats, cfg.blocks_y, stream);
+  }
+  const Gas<float> G = make_gas<float>(gamma, opt);
+  if (dir == HYDRO_DIR_X)
+    return launch_sweep_x<float>(batch_of<float>(*this, src, dst, cfg.seg_x, items_x), G, stats,
+                                 cfg.blocks_x, stream);
+  return launch_sweep_y<float>(batch_of<float>(*this, src, dst, cfg.seg_y, items_y), G, fuse_dt,
+                               stats, cfg.blocks_y, stream);
+}
+
+hipError_t Plan::enqueue_step() {
+  if (!acc_valid) {
+    PhaseTimer pt(this, HYDRO_PHASE_DT);
+    HIP_TRY(enqueue_max_speed());
+  }
+  {
+    PhaseTimer pt(this, HYDRO_PHASE_DT);
+    HIP_TRY(enqueue_finalize(true, true));
+  }
+  {
+    PhaseTimer pt(this, HYDRO_PHASE_SWEEP_X);
+    HIP_TRY(enqueue_sweep(HYDRO_DIR_X, false, U, V));
+  }
+  {
+    PhaseTimer pt(this, HYDRO_PHASE_SWEEP_Y);
+    HIP_TRY(enqueue_sweep(HYDRO_DIR_Y, true, V, U));
+  }
+  acc_valid = true;
+  return hipSuccess;
+}
+
+hipError_t Plan::enqueue_single_sweep(int dir) {
+  HIP_TRY(enqueue_sweep(dir, false, U, V));
+  acc_valid = false;
+  if (dtype == HYDRO_F64) return launch_copy<double>(batch_of<double>(*this, V, U, 0, rows), stream);
+  return launch_copy<float>(batch_of<float>(*this, V, U, 0, rows), stream);
+}
+
+hipError_t Plan::enqueue_totals() {
+  if (dtype == HYDRO_F64)
+    return launch_totals<double>(batch_of<double>(*this, U, nullptr, 0, rows), tot_blocks,
+                                 partials, stream);
+  return launch_totals<float>(batch_of<float>(*this, U, nullptr, 0, rows), tot_blocks, partials,
+                              stream);
+}
+
+hipError_t Plan::graph_launch(int nsteps) {
+  if (!acc_valid) {
+    // the graph starts from a valid max speed; compute it eagerly once
+    HIP_TRY(enqueue_max_speed());
+    acc_valid = true;
+  }
+  if (!gexec || graph_steps != nsteps) {
+    drop_graph();
+    const bool prof = profiling;
+    profiling = false;
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = enqueue_step();
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(stream, &graph);
+    profiling = prof;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return e;
+    }
+    graph_steps = nsteps;
+  }
+  return hipGraphLaunch(gexec, stream);
+}
+
+hipError_t Plan::sync_states(std::vector<DevState>& out) {
+  out.resize(n);
+  HIP_TRY(hipMemcpyAsync(out.data(), st, sizeof(DevState) * n, hipMemcpyDeviceToHost, stream));
+  return hipStreamSynchronize(stream);
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, std::vector<int>>, LaunchCfg> g_tune_cache;
+
+std::tuple<int, std::vector<int>> tune_key(const Plan& p) {
+  std::vector<int> shape;
+  shape.reserve(3 * p.n);
+  for (int g = 0; g < p.n; ++g) {
+    shape.push_back(p.nx[g]);
+    shape.push_back(p.ny[g]);
+    shape.push_back(p.bc[g]);
+  }
+  return {p.dtype, shape};
+}
+
+}  // namespace
+
+hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
+  const auto key = tune_key(*this);
+  LaunchCfg best = cfg;
+  double best_x = -1.0, best_y = -1.0;
+  int tried = 0;
+  bool cached = false;
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    const LaunchCfg saved = cfg;
+    // sweeps read U and write V only; dt must be set for the kernels to run
+    HIP_TRY(enqueue_max_speed());
+    HIP_TRY(enqueue_finalize(false, false));
+    const unsigned persist[] = {0u, (unsigned)(cus * 2), (unsigned)(cus * 4), (unsigned)(cus * 8)};
+    auto time_it = [&](int dir, double& ms) -> hipError_t {
+      HIP_TRY(upload_descriptors());
+      HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));  // warm-up
+      HIP_TRY(hipEventRecord(a, stream));
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
+      HIP_TRY(hipEventRecord(b, stream));
+      HIP_TRY(hipEventSynchronize(b));
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, a, b));
+      ms = t / reps;
+      return hipSuccess;
+    };
+    const int segx[] = {1, 2, 4, 8};
+    const int segy[] = {32, 64, 128, 256, 512};
+    int maxny = 0;
+    for (int g = 0; g < n; ++g) maxny = std::max(maxny, ny[g]);
+    for (int sx : segx) {
+      if (user_seg_x && sx != saved.seg_x) continue;
+      for (unsigned pb : persist) {
+        cfg = saved;
+        cfg.seg_x = sx;
+        cfg.blocks_x = pb;
+        double ms;
+        HIP_TRY(time_it(HYDRO_DIR_X, ms));
+        ++tried;
+        if (best_x < 0 || ms < best_x) {
+          best_x = ms;
+          best.seg_x = sx;
+          best.blocks_x = pb;
+        }
+      }
+    }
+    for (int sy : segy) {
+      if (user_seg_y && sy != saved.seg_y) continue;
+      if (!user_seg_y && sy > 2 * maxny && sy != 32) continue;
+      for (unsigned pb : persist) {
+        cfg = saved;
+        cfg.seg_y = sy;
+        cfg.blocks_y = pb;
+        double ms;
+        HIP_TRY(time_it(HYDRO_DIR_Y, ms));
+        ++tried;
+        if (best_y < 0 || ms < best_y) {
+          best_y = ms;
+          best.seg_y = sy;
+          best.blocks_y = pb;
+        }
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  cfg = best;
+  acc_valid = false;  // the timing runs accumulated into st[].acc
+  HIP_TRY(upload_descriptors());
+  if (out) {
+    out->seg_x = best.seg_x;
+    out->seg_y = best.seg_y;
+    out->blocks_x = best.blocks_x;
+    out->blocks_y = best.blocks_y;
+    out->ms_x = best_x;
+    out->ms_y = best_y;
+    out->candidates = tried;
+    out->cached = cached ? 1 : 0;
+  }
+  return hipSuccess;
+}
+
+}  // namespace hydro

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (HYDRO_BC_OUTFLOW, HYDRO_BC_PERIODIC, HYDRO_BC_REFLECT, HYDRO_DIR_X,
                    HYDRO_DIR_Y, HYDRO_F32, HYDRO_F64, HydroError, check)
 
-__all__ = ["Hydro", "HydroError", "BC", "DIR_X", "DIR_Y"]
+__all__ = ["Hydro", "HydroBatch", "HydroError", "BC", "DIR_X", "DIR_Y"]
 
 BC = {"reflect": HYDRO_BC_REFLECT, "outflow": HYDRO_BC_OUTFLOW, "periodic": HYDRO_BC_PERIODIC}
 DIR_X, DIR_Y = HYDRO_DIR_X, HYDRO_DIR_Y
@@ -159,9 +159,158 @@ class Hydro:
         ms = (ctypes.c_double * _lib.HYDRO_NPHASES)()
         n = (ctypes.c_longlong * _lib.HYDRO_NPHASES)()
         check(self.lib.hydro_get_profile(self.handle, ms, n, int(reset)))
-        return {name: {"ms": ms[k], "launches": n[k]} for k, name in enumerate(_lib.PHASE_NAMES)}
+        return _profile_dict(ms, n)
 
     def stats(self, reset: bool = False) -> dict:
         s = _lib.hydro_stats_t()
         check(self.lib.hydro_riemann_stats(self.handle, ctypes.byref(s), int(reset)))
-        return {"interfaces": s.interfaces, "hist": list(s.hist), "fallbacks": s.fallbacks}
+        return _stats_dict(s)
+
+    def autotune(self, use_cache: bool = True) -> dict:
+        """Pick the fastest launch shape of both sweeps on the bound state."""
+        t = _lib.hydro_tune_t()
+        check(self.lib.hydro_autotune(self.handle, ctypes.byref(t), int(use_cache)))
+        return _tune_dict(t)
+
+
+def _stats_dict(s) -> dict:
+    return {"interfaces": s.interfaces, "hist": list(s.hist), "fallbacks": s.fallbacks}
+
+
+def _tune_dict(t) -> dict:
+    return {k: getattr(t, k) for k, _ in t._fields_}
+
+
+def _profile_dict(ms, n) -> dict:
+    return {name: {"ms": ms[k], "launches": n[k]} for k, name in enumerate(_lib.PHASE_NAMES)}
+
+
+class HydroBatch:
+    """Independent grids of uneven sizes advanced together: one kernel launch
+    per sweep over all of them, each grid with its own dt and clock.
+
+    ``shapes`` is a list of (nx, ny); ``bc`` one boundary type or one per grid.
+    The packed state lives in ``self.buf`` (1D torch tensor, layout of
+    hydro_batch_layout); ``self.view(g)`` is grid g's [4, ny, nx] view.
+    """
+
+    def __init__(self, shapes, gamma: float = 1.4, cfl: float = 0.8, bc="reflect",
+                 dtype: torch.dtype = torch.float32, device="cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.lib = _lib.load()
+        if dtype not in _DTYPE:
+            raise ValueError(f"dtype {dtype}: float64 or float32")
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        self.n = len(self.shapes)
+        bcs = [_bc_code(bc)] * self.n if not isinstance(bc, (list, tuple)) else [
+            _bc_code(b) for b in bc]
+        nx = (ctypes.c_int * self.n)(*[s[0] for s in self.shapes])
+        ny = (ctypes.c_int * self.n)(*[s[1] for s in self.shapes])
+        bcc = (ctypes.c_int * self.n)(*bcs)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.handle = self.lib.hydro_batch_create(self.n, nx, ny, float(gamma), float(cfl), bcc)
+            if not self.handle:
+                raise HydroError(_lib.HYDRO_EINVAL, _lib.last_error())
+            offs = (ctypes.c_longlong * self.n)()
+            pitches = (ctypes.c_long * self.n)()
+            total = self.lib.hydro_batch_layout(self.handle, _DTYPE[dtype], offs, pitches)
+            if total < 0:
+                raise HydroError(int(total), _lib.last_error())
+            self.offsets = list(offs)
+            self.pitches = list(pitches)
+            self.buf = torch.zeros(int(total), dtype=dtype, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            check(self.lib.hydro_batch_bind(self.handle, ctypes.c_void_p(self.buf.data_ptr()),
+                                            _DTYPE[dtype], ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            self.lib.hydro_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view(self, g: int) -> torch.Tensor:
+        nx, ny = self.shapes[g]
+        p = self.pitches[g]
+        o = self.offsets[g]
+        return self.buf[o: o + 4 * ny * p].view(4, ny, p)[:, :, :nx]
+
+    def set_states(self, states) -> None:
+        self.stream.synchronize()
+        torch.cuda.synchronize(self.device)
+        for g, U in enumerate(states):
+            t = torch.as_tensor(np.asarray(U) if not isinstance(U, torch.Tensor) else U)
+            nx, ny = self.shapes[g]
+            if tuple(t.shape) != (4, ny, nx):
+                raise ValueError(f"grid {g}: shape {tuple(t.shape)} != (4, {ny}, {nx})")
+            self.view(g).copy_(t.to(device=self.device, dtype=self.dtype))
+        torch.cuda.synchronize(self.device)
+        check(self.lib.hydro_batch_invalidate(self.handle))
+
+    def get_states(self) -> list:
+        self.stream.synchronize()
+        return [self.view(g).detach().to("cpu").numpy().copy() for g in range(self.n)]
+
+    def set_options(self, **kw) -> None:
+        o = _lib.hydro_options_t(niter=10, tol=1e-8, guess=0, stats=0, seg_x=0, seg_y=0)
+        for k, v in getattr(self, "_opts", {}).items():
+            setattr(o, k, v)
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        check(self.lib.hydro_batch_set_options(self.handle, ctypes.byref(o)))
+        self._opts = {k: getattr(o, k) for k, _ in o._fields_}
+
+    def compute_dt(self) -> np.ndarray:
+        out = (ctypes.c_double * self.n)()
+        check(self.lib.hydro_batch_compute_dt(self.handle, out))
+        return np.array(list(out))
+
+    def step(self, n: int = 1) -> None:
+        for _ in range(n):
+            check(self.lib.hydro_batch_step(self.handle))
+
+    def graph_steps(self, nsteps: int) -> None:
+        check(self.lib.hydro_batch_graph_steps(self.handle, int(nsteps)))
+
+    def totals(self) -> np.ndarray:
+        out = (ctypes.c_double * (4 * self.n))()
+        check(self.lib.hydro_batch_totals(self.handle, out))
+        return np.array(list(out)).reshape(self.n, 4)
+
+    def clock(self):
+        t = (ctypes.c_double * self.n)()
+        st = (ctypes.c_long * self.n)()
+        dt = (ctypes.c_double * self.n)()
+        check(self.lib.hydro_batch_get_clock(self.handle, t, st, dt))
+        return np.array(list(t)), np.array(list(st)), np.array(list(dt))
+
+    def stats(self, reset: bool = False) -> dict:
+        s = _lib.hydro_stats_t()
+        check(self.lib.hydro_batch_riemann_stats(self.handle, ctypes.byref(s), int(reset)))
+        return _stats_dict(s)
+
+    def autotune(self, use_cache: bool = True) -> dict:
+        t = _lib.hydro_tune_t()
+        check(self.lib.hydro_batch_autotune(self.handle, ctypes.byref(t), int(use_cache)))
+        return _tune_dict(t)
+
+    def set_profiling(self, enable: bool = True) -> None:
+        check(self.lib.hydro_batch_set_profiling(self.handle, int(enable)))
+
+    def profile(self, reset: bool = True) -> dict:
+        ms = (ctypes.c_double * _lib.HYDRO_NPHASES)()
+        n = (ctypes.c_longlong * _lib.HYDRO_NPHASES)()
+        check(self.lib.hydro_batch_get_profile(self.handle, ms, n, int(reset)))
+        return _profile_dict(ms, n)
