@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-updates/s per split step & HBM GB/s vs peak; learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_fourier_blasts_8192_pmc.json")
-KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/godunov.hpp"]
+KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/godunov.hpp",
+                  "paper_2106_13465_amd/csrc/fastmath.hpp", "paper_2106_13465_amd/csrc/device_state.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -55,7 +56,7 @@ def workload(name: str, n: int):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0):
+def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True):
     import torch
 
     from paper_2106_13465_amd.hydro import Hydro
@@ -66,6 +67,7 @@ def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0):
     if seg_x or seg_y:
         h.set_options(seg_x=seg_x, seg_y=seg_y)
     h.set_state(U)
+    tune = h.autotune(use_cache=True) if autotune else None
     h.step(warmup)
     torch.cuda.synchronize()
     h.profile(reset=True)
@@ -84,7 +86,7 @@ def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0):
     h.set_profiling(False)
     t, nsteps, dt = h.clock()
     return h, {"ms_total": ms_total, "wall_s": wall, "profile": prof, "t": t, "steps_done": nsteps,
-               "dt": dt}
+               "dt": dt, "tune": tune}
 
 
 def newton_report(h):
@@ -140,6 +142,139 @@ def cpu_baseline(U, bc_name):
                       f"{oracle.threads()} OpenMP threads over pencils"}
 
 
+BATCH_WORKLOADS = {
+    "multiblast_batch": ("reflect", 100, (
+        "multiblast_batch: 256 square grids, side log-uniform 64..1024 (sum of cells "
+        "{cells}), rho 1, u = v = 0, p log-uniform 1e-5..1, 1-8 blasts per grid with energy "
+        "log-uniform 1e-2..1e2; reflective")),
+    "quadrant_batch": ("outflow", 200, (
+        "quadrant_batch: 64 square grids, side log-uniform 512..2048 (sum of cells {cells}), "
+        "four constant states with rho, p log-uniform 0.1..2 (2e-5..2 for p in 10% of grids), "
+        "u, v uniform -1..1; outflow")),
+}
+
+
+def bench_batch(args) -> dict:
+    """Batched workloads: one persistent launch per sweep over all grids, the
+    step captured in a HIP graph; compared with a loop of per-grid handles."""
+    import numpy as np
+    import torch
+
+    from paper_2106_13465_amd import inputs
+    from paper_2106_13465_amd.hydro import Hydro, HydroBatch
+
+    bc, default_steps, desc = BATCH_WORKLOADS[args.workload]
+    steps = args.steps if args.steps_given else default_steps
+    print(f"# generating {args.workload}", file=sys.stderr, flush=True)
+    grids = (inputs.multiblast_batch() if args.workload == "multiblast_batch"
+             else inputs.quadrant_batch())
+    shapes = [(U.shape[2], U.shape[1]) for U in grids]
+    cells = sum(nx * ny for nx, ny in shapes)
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    elem = 8 if args.dtype == "f64" else 4
+    b = HydroBatch(shapes, 1.4, 0.8, bc, dtype=dtype, device="cuda:0")
+    b.set_states(grids)
+    tune = None if args.no_autotune else b.autotune(use_cache=True)
+    graph_n = min(steps, 50)
+    # warmup (also captures the graph)
+    b.step(args.warmup)
+    b.graph_steps(graph_n)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    done = 0
+    start.record(b.stream)
+    while done + graph_n <= steps:
+        b.graph_steps(graph_n)
+        done += graph_n
+    b.step(steps - done)
+    stop.record(b.stream)
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    # per-kernel times from an eager, profiled pass of a few steps
+    b.set_profiling(True)
+    b.profile(reset=True)
+    b.step(10)
+    prof = b.profile(reset=True)
+    b.set_profiling(False)
+    sx = sweep_record(cells, elem, prof["sweep_x"])
+    sy = sweep_record(cells, elem, prof["sweep_y"])
+    b.set_options(stats=1)
+    b.stats(reset=True)
+    b.step(1)
+    st = b.stats(reset=True)
+    b.set_options(stats=0)
+    hist = st["hist"]
+    conv = sum(hist[1:])
+    newton = {"interfaces": st["interfaces"], "unconverged": hist[0],
+              "mean_iterations": sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1)}
+    t, n, _ = b.clock()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+
+    # baseline: one handle per grid, eager steps in a loop (3 launches per grid per step)
+    print("# per-grid launch loop", file=sys.stderr, flush=True)
+    hs = []
+    for U in grids:
+        h = Hydro(U.shape[2], U.shape[1], 1.4, 0.8, bc, dtype=dtype, device="cuda:0")
+        h.set_state(U)
+        hs.append(h)
+    loop_steps = max(1, min(steps, 20))
+    for h in hs:
+        h.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(loop_steps):
+        for h in hs:
+            h.step(1)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3 / loop_steps
+    for h in hs:
+        h.close()
+    del hs
+    torch.cuda.empty_cache()
+
+    ms_step = ms_total / steps
+    dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
+    line = {
+        "metric": METRIC, "value": 2.0 * cells * steps / (ms_total * 1e-3),
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": desc.format(cells=cells), "grids": len(grids), "cells": cells,
+                   "bc": bc, "gamma": 1.4, "cfl": 0.8, "graph_steps_per_replay": graph_n,
+                   "parallelism": "single GPU, one persistent launch per sweep"},
+        "sweeps": {"x": sx, "y": sy},
+        "launch_shape": tune,
+        "newton": newton,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
+                     "traffic": pmc_traffic(dom_name + "_batch", args.dtype),
+                     "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
+                     "avg_launch_ms": dom["avg_ms"]},
+        "per_grid_loop": {"ms_per_step": loop_ms, "speedup_of_batched_graph": loop_ms / ms_step},
+        "sim_time": {"min": float(np.min(t)), "max": float(np.max(t))},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        sample = grids[:16]
+        t0 = time.perf_counter()
+        cu = 0
+        for U, (nx, ny) in zip(sample, shapes[:16]):
+            V = U.copy()
+            oracle.step(V, oracle.cfg(bc={"reflect": 1, "outflow": 2, "periodic": 3}[bc]))
+            cu += 2 * nx * ny
+        sec = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": cu / sec, "unit": "cell-updates/s",
+                                "cores": oracle.threads(), "kind": "oracle", "seconds": sec,
+                                "sample": f"1 step of the first 16 grids ({cu // 2} cells), FP64, "
+                                          f"{oracle.threads()} OpenMP threads"}
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +282,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--workload", default="fourier_blasts",
-                    choices=["fourier_blasts", "shear_layer", "blast_corner"])
+                    choices=["fourier_blasts", "shear_layer", "blast_corner", "multiblast_batch",
+                             "quadrant_batch"])
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -156,6 +293,8 @@ def main() -> int:
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a plain device copy of the state (counter calibration)")
     args = ap.parse_args()
+    args.steps_given = "--steps" in sys.argv
+    args.dtype_given = "--dtype" in sys.argv
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -166,6 +305,12 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.workload in BATCH_WORKLOADS:
+        if args.dtype == "f64" and not args.dtype_given:
+            args.dtype = "f32"
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
 
     print(f"# generating {args.workload} {args.size}^2", file=sys.stderr, flush=True)
     U, bc, desc = workload(args.workload, args.size)
@@ -178,7 +323,8 @@ def main() -> int:
     for dn in variants:
         print(f"# gpu {dn}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
               flush=True)
-        h, r = run_gpu(U, bc, dn, args.steps, args.warmup, args.seg_x, args.seg_y)
+        h, r = run_gpu(U, bc, dn, args.steps, args.warmup, args.seg_x, args.seg_y,
+                       not args.no_autotune)
         elem = 8 if dn == "f64" else 4
         ms_step = r["ms_total"] / args.steps
         sx = sweep_record(cells, elem, r["profile"]["sweep_x"])
@@ -189,6 +335,7 @@ def main() -> int:
             "sweeps": {"x": sx, "y": sy},
             "dt_phase_avg_ms": r["profile"]["dt"]["ms"] / max(r["profile"]["dt"]["launches"], 1),
             "sim_time": r["t"],
+            "launch_shape": r["tune"],
         }
         states[dn] = h.get_state()
         results[dn]["newton"] = newton_report(h)
@@ -230,6 +377,7 @@ def main() -> int:
                    "limiter": "minmod", "newton_cap": 10, "newton_tol": 1e-8,
                    "parallelism": "single GPU"},
         "sweeps": res["sweeps"],
+        "launch_shape": res["launch_shape"],
         "newton": res["newton"],
         "roofline": roofline,
     }
