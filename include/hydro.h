@@ -44,6 +44,8 @@
 #ifndef HYDRO_H
 #define HYDRO_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -182,6 +184,58 @@ int hydro_get_profile(hydro_t *h, double ms[HYDRO_NPHASES], long long launches[H
                       int reset);
 
 /* ------------------------------------------------------------------------
+ * Learned starting guess for the star pressure (an addition to the paper's
+ * method; the two-rarefaction guess with the full Newton cap stays the
+ * fallback).  A 6 -> 32 -> 32 -> 1 network with ReLU activations, BF16 weights
+ * and activations on the MFMA units, FP32 accumulation.  Features of an
+ * interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar), w = (u_L-u_bar)/c_bar,
+ * x = (a, b, w, -a, -b, -w) with geometric means rho_bar, p_bar, u_bar the
+ * mean velocity and c_bar = sqrt(gamma p_bar/rho_bar); output
+ * y ~ ln(p_star / p_bar).  In a sweep with options.guess = HYDRO_GUESS_MLP, Newton
+ * runs at most 4 iterations from p_bar exp(y); if its convergence test fails
+ * (or the guess is not a finite positive pressure) the interface restarts
+ * from the two-rarefaction guess with the full cap and counts as a fallback.
+ *
+ * Parameters: HYDRO_MLP_PARAMS FP32 values, flat and row-major:
+ * W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3.  All pointers below are
+ * device memory owned by the caller; all calls are asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+#define HYDRO_MLP_PARAMS 1313
+
+/* Bytes of the packed device network (BF16 weights in MFMA lane order). */
+size_t hydro_mlp_dev_bytes(void);
+/* Pack FP32 parameters into a device network (and mark it invalid if any
+ * parameter is not finite: then every learned guess falls back). */
+int hydro_mlp_pack(const float *params, void *mlp, void *stream);
+/* Logged interface records [n][8] -> features X [n][6] and targets
+ * Y [n] = ln(p_star / p_bar) (Y may be NULL). */
+int hydro_mlp_features(const float *records, long long n, double gamma, float *X, float *Y,
+                       void *stream);
+/* Y[n] = network output for X [n][6]. */
+int hydro_mlp_forward(const void *mlp, const float *X, float *Y, long long n, void *stream);
+/* Gradient of the mean squared error (1/n) sum (y - T)^2 with respect to the
+ * parameters (grad[HYDRO_MLP_PARAMS], overwritten) and the loss (may be NULL),
+ * using scratch of hydro_mlp_grad_scratch_bytes(n). */
+size_t hydro_mlp_grad_scratch_bytes(long long n);
+int hydro_mlp_grad(const void *mlp, const float *X, const float *T, long long n, float *scratch,
+                   float *grad, float *loss, void *stream);
+/* One Adam step (step >= 1 for the bias correction) on FP32 master
+ * parameters with moment buffers m, v; repack with hydro_mlp_pack after. */
+int hydro_mlp_adam(float *params, float *m, float *v, const float *grad, long long step,
+                   double lr, double beta1, double beta2, double eps, void *stream);
+/* Use a packed network (borrowed; NULL detaches it) for HYDRO_GUESS_MLP. */
+int hydro_set_mlp(hydro_t *h, const void *mlp);
+/* Interface-state logger: while records != NULL, every sweep offers each
+ * interface with probability rate_smooth (rate_strong when the jump
+ * |ln(p_L/p_R)| + |u_R-u_L|/c_bar exceeds 0.05) and appends
+ * (rho_L, u_L, p_L, rho_R, u_R, p_R, p*, jump) as 8 floats until capacity
+ * records are stored.  Seeded hash per (grid, step, interface, direction). */
+int hydro_set_logger(hydro_t *h, float *records, long long capacity, unsigned long long seed,
+                     double rate_smooth, double rate_strong);
+/* Records offered so far (stored: min(count, capacity)); synchronises. */
+long long hydro_logger_count(hydro_t *h);
+
+/* ------------------------------------------------------------------------
  * Batches: n independent grids of uneven sizes advanced together, one kernel
  * launch per sweep over all of them (persistent wave loop over a work list
  * of (grid, segment) items), each grid with its own dt, clock and status.
@@ -223,6 +277,10 @@ int hydro_batch_autotune(hydro_batch_t *b, hydro_tune_t *out, int use_cache);
 int hydro_batch_set_profiling(hydro_batch_t *b, int enable);
 int hydro_batch_get_profile(hydro_batch_t *b, double ms[HYDRO_NPHASES],
                             long long launches[HYDRO_NPHASES], int reset);
+int hydro_batch_set_mlp(hydro_batch_t *b, const void *mlp);
+int hydro_batch_set_logger(hydro_batch_t *b, float *records, long long capacity,
+                           unsigned long long seed, double rate_smooth, double rate_strong);
+long long hydro_batch_logger_count(hydro_batch_t *b);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,11 @@ def _load():
             ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg), _LL]),
         "oracle_totals": (None, [_D, ctypes.c_int, ctypes.c_int, _D]),
         "oracle_threads": (ctypes.c_int, []),
+        "mlp_oracle_nparams": (ctypes.c_int, []),
+        "mlp_oracle_bf16": (ctypes.c_double, [ctypes.c_double]),
+        "mlp_oracle_forward": (ctypes.c_double, [_D, _D, ctypes.c_int, _D]),
+        "mlp_oracle_loss_grad": (None, [_D, _D, _D, ctypes.c_long, ctypes.c_int, _D, _D]),
+        "mlp_oracle_features": (None, [_D, ctypes.c_double, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -225,3 +230,43 @@ def totals(U: np.ndarray) -> np.ndarray:
 
 def threads() -> int:
     return _load().oracle_threads()
+
+
+# ---------------------------------------------------------------- learned-guess network
+MLP_PARAMS = 1313
+
+
+def mlp_bf16(v: float) -> float:
+    return _load().mlp_oracle_bf16(float(v))
+
+
+def mlp_forward(params, X, emulate=True) -> np.ndarray:
+    """Network outputs for X [n, 6] (FP64; emulate = BF16 rounding points)."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 6)
+    lib = _load()
+    return np.array([lib.mlp_oracle_forward(_dptr(P), _dptr(np.ascontiguousarray(x)),
+                                            int(emulate), None) for x in X])
+
+
+def mlp_loss_grad(params, X, T, emulate=True):
+    """(grad [1313], loss) of the mean squared error."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 6)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
+    g = np.zeros(MLP_PARAMS)
+    loss = ctypes.c_double()
+    _load().mlp_oracle_loss_grad(_dptr(P), _dptr(X), _dptr(T), len(T), int(emulate), _dptr(g),
+                                 ctypes.byref(loss))
+    return g, loss.value
+
+
+def mlp_features(record, gamma=1.4):
+    """(x [6], target) of one interface record (rho_L, u_L, p_L, rho_R, u_R, p_R, p*, .)."""
+    rec = np.ascontiguousarray(np.asarray(record, dtype=np.float64).reshape(-1)[:8])
+    if rec.size < 8:
+        rec = np.concatenate([rec, np.zeros(8 - rec.size)])
+    x = np.zeros(6)
+    t = ctypes.c_double()
+    _load().mlp_oracle_features(_dptr(rec), gamma, _dptr(x), ctypes.byref(t))
+    return x, t.value

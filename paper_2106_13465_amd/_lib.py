@@ -90,6 +90,19 @@ SIGNATURES = {
     "hydro_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "hydro_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_tune_t), ctypes.c_int]),
+    # learned guess
+    "hydro_mlp_dev_bytes": (ctypes.c_size_t, []),
+    "hydro_mlp_pack": (ctypes.c_int, [_vp, _vp, _vp]),
+    "hydro_mlp_features": (ctypes.c_int, [_vp, ctypes.c_longlong, ctypes.c_double, _vp, _vp, _vp]),
+    "hydro_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_longlong, _vp]),
+    "hydro_mlp_grad_scratch_bytes": (ctypes.c_size_t, [ctypes.c_longlong]),
+    "hydro_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_longlong, _vp, _vp, _vp, _vp]),
+    "hydro_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_longlong, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
+    "hydro_set_mlp": (ctypes.c_int, [_vp, _vp]),
+    "hydro_set_logger": (ctypes.c_int, [_vp, _vp, ctypes.c_longlong, ctypes.c_ulonglong,
+                                        ctypes.c_double, ctypes.c_double]),
+    "hydro_logger_count": (ctypes.c_longlong, [_vp]),
     # batches
     "hydro_batch_create": (_vp, [ctypes.c_int, _I, _I, ctypes.c_double, ctypes.c_double, _I]),
     "hydro_batch_destroy": (None, [_vp]),
@@ -107,6 +120,10 @@ SIGNATURES = {
     "hydro_batch_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_batch_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong),
                                                ctypes.c_int]),
+    "hydro_batch_set_mlp": (ctypes.c_int, [_vp, _vp]),
+    "hydro_batch_set_logger": (ctypes.c_int, [_vp, _vp, ctypes.c_longlong, ctypes.c_ulonglong,
+                                              ctypes.c_double, ctypes.c_double]),
+    "hydro_batch_logger_count": (ctypes.c_longlong, [_vp]),
 }
 
 _lib = None

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhydro.so")
 # (source, floating-point contraction)
-SOURCES = [("api.cpp", "off"), ("plan.cpp", "off"), ("kernels.hip", "fast")]
+SOURCES = [("api.cpp", "off"), ("plan.cpp", "off"), ("kernels.hip", "fast"),
+           ("mlp_kernels.hip", "fast")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

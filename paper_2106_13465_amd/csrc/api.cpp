@@ -13,6 +13,8 @@
 
 #include "hydro.h"
 #include "launch.hpp"
+#include "mlp.hpp"
+#include "mlp_launch.hpp"
 #include "plan.hpp"
 
 struct hydro_s : hydro::Plan {};
@@ -91,13 +93,15 @@ int check_bound(const hydro::Plan* p) {
   return HYDRO_OK;
 }
 
-int check_options(const hydro_options_t* o) {
+int check_options(const hydro::Plan* p, const hydro_options_t* o) {
   if (!o) return fail(HYDRO_EINVAL, "NULL options");
   if (o->niter < 1 || o->niter > HYDRO_MAX_NITER)
     return fail(HYDRO_EINVAL, "niter %d: must be in 1..%d", o->niter, HYDRO_MAX_NITER);
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(HYDRO_EINVAL, "tol %g", o->tol);
-  if (o->guess != HYDRO_GUESS_PTR)
-    return fail(HYDRO_EINVAL, "guess %d not available on this handle", o->guess);
+  if (o->guess != HYDRO_GUESS_PTR && o->guess != HYDRO_GUESS_MLP)
+    return fail(HYDRO_EINVAL, "guess %d", o->guess);
+  if (o->guess == HYDRO_GUESS_MLP && !p->mlp)
+    return fail(HYDRO_ESTATE, "learned guess requested but no network set (hydro_set_mlp)");
   if (o->seg_x < 0 || o->seg_x > 4096) return fail(HYDRO_EINVAL, "seg_x %d", o->seg_x);
   if (o->seg_y < 0 || o->seg_y > (1 << 20)) return fail(HYDRO_EINVAL, "seg_y %d", o->seg_y);
   return HYDRO_OK;
@@ -218,7 +222,7 @@ int do_stats(hydro::Plan* p, hydro_stats_t* out, int reset) {
 
 int do_set_options(hydro::Plan* p, const hydro_options_t* o) {
   if (!p) return fail(HYDRO_EINVAL, "NULL handle");
-  int rc = check_options(o);
+  int rc = check_options(p, o);
   if (rc) return rc;
   DeviceGuard g(p->device);
   hipError_t e = p->set_options(*o);
@@ -294,6 +298,42 @@ int do_bind(hydro::Plan* p, void* U, const long* pitches, const long long* offse
   if (e == hipErrorOutOfMemory) return fail(HYDRO_ENOMEM, "second state buffer: out of memory");
   if (e != hipSuccess) return dev_fail(e, "bind");
   return HYDRO_OK;
+}
+
+int do_set_mlp(hydro::Plan* p, const void* mlp) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  if (mlp) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, mlp) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return fail(HYDRO_EINVAL, "network pointer is not device memory");
+    }
+  }
+  p->mlp = static_cast<const hydro::MlpDev*>(mlp);
+  if (!mlp && p->opt.guess == HYDRO_GUESS_MLP) p->opt.guess = HYDRO_GUESS_PTR;
+  p->drop_graph();
+  return HYDRO_OK;
+}
+
+int do_set_logger(hydro::Plan* p, float* buf, long long cap, unsigned long long seed, double rs,
+                  double rg) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  if (buf && cap < 1) return fail(HYDRO_EINVAL, "logger capacity %lld", cap);
+  if (!(rs >= 0.0 && rs <= 1.0 && rg >= 0.0 && rg <= 1.0))
+    return fail(HYDRO_EINVAL, "logger rates %g %g: must be in [0, 1]", rs, rg);
+  DeviceGuard g(p->device);
+  hipError_t e = p->set_logger(buf, cap, seed, rs, rg);
+  if (e != hipSuccess) return dev_fail(e, "set_logger");
+  return HYDRO_OK;
+}
+
+long long do_logger_count(hydro::Plan* p) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  DeviceGuard g(p->device);
+  unsigned long long c = 0;
+  hipError_t e = p->logger_count(&c);
+  if (e != hipSuccess) return dev_fail(e, "logger_count");
+  return (long long)c;
 }
 
 }  // namespace
@@ -435,6 +475,74 @@ int hydro_batch_set_profiling(hydro_batch_t* b, int enable) { return do_set_prof
 int hydro_batch_get_profile(hydro_batch_t* b, double ms[HYDRO_NPHASES],
                             long long launches[HYDRO_NPHASES], int reset) {
   return do_get_profile(b, ms, launches, reset);
+}
+
+int hydro_set_mlp(hydro_t* h, const void* mlp) { return do_set_mlp(h, mlp); }
+int hydro_batch_set_mlp(hydro_batch_t* b, const void* mlp) { return do_set_mlp(b, mlp); }
+int hydro_set_logger(hydro_t* h, float* records, long long capacity, unsigned long long seed,
+                     double rate_smooth, double rate_strong) {
+  return do_set_logger(h, records, capacity, seed, rate_smooth, rate_strong);
+}
+int hydro_batch_set_logger(hydro_batch_t* b, float* records, long long capacity,
+                           unsigned long long seed, double rate_smooth, double rate_strong) {
+  return do_set_logger(b, records, capacity, seed, rate_smooth, rate_strong);
+}
+long long hydro_logger_count(hydro_t* h) { return do_logger_count(h); }
+long long hydro_batch_logger_count(hydro_batch_t* b) { return do_logger_count(b); }
+
+// ------------------------------------------------------------ learned-guess network
+size_t hydro_mlp_dev_bytes(void) { return sizeof(hydro::MlpDev); }
+
+size_t hydro_mlp_grad_scratch_bytes(long long n) {
+  return sizeof(float) * hydro::mlp_grad_scratch_floats(n < 1 ? 1 : n);
+}
+
+int hydro_mlp_pack(const float* params, void* mlp, void* stream) {
+  if (!params || !mlp) return fail(HYDRO_EINVAL, "NULL argument");
+  hipError_t e = hydro::launch_mlp_pack(params, static_cast<hydro::MlpDev*>(mlp),
+                                        (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_mlp_pack");
+  return HYDRO_OK;
+}
+
+int hydro_mlp_features(const float* records, long long n, double gamma, float* X, float* Y,
+                       void* stream) {
+  if (!records || !X || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
+  if (!(gamma > 1.0)) return fail(HYDRO_EINVAL, "gamma %g", gamma);
+  if (n == 0) return HYDRO_OK;
+  hipError_t e = hydro::launch_mlp_features(records, n, (float)gamma, X, Y, (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_mlp_features");
+  return HYDRO_OK;
+}
+
+int hydro_mlp_forward(const void* mlp, const float* X, float* Y, long long n, void* stream) {
+  if (!mlp || !X || !Y || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
+  if (n == 0) return HYDRO_OK;
+  hipError_t e = hydro::launch_mlp_forward(static_cast<const hydro::MlpDev*>(mlp), X, Y, n,
+                                           (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_mlp_forward");
+  return HYDRO_OK;
+}
+
+int hydro_mlp_grad(const void* mlp, const float* X, const float* T, long long n, float* scratch,
+                   float* grad, float* loss, void* stream) {
+  if (!mlp || !X || !T || !scratch || !grad || n < 1) return fail(HYDRO_EINVAL, "bad arguments");
+  hipError_t e = hydro::launch_mlp_grad(static_cast<const hydro::MlpDev*>(mlp), X, T, n, scratch,
+                                        grad, loss, (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_mlp_grad");
+  return HYDRO_OK;
+}
+
+int hydro_mlp_adam(float* params, float* m, float* v, const float* grad, long long step,
+                   double lr, double beta1, double beta2, double eps, void* stream) {
+  if (!params || !m || !v || !grad || step < 1) return fail(HYDRO_EINVAL, "bad arguments");
+  if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(HYDRO_EINVAL, "Adam hyper-parameters");
+  hipError_t e = hydro::launch_mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps,
+                                        (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_mlp_adam");
+  return HYDRO_OK;
 }
 
 }  // extern "C"

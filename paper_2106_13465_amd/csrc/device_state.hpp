@@ -35,8 +35,25 @@ struct DevState {
   double totals[4];
   unsigned long long interfaces;          // Riemann problems counted
   unsigned long long hist[kMaxIter + 1];  // [0] unconverged, [k] k iterations
-  unsigned long long fallbacks;
+  unsigned long long fallbacks;           // learned guesses rejected
 };
+
+struct MlpDev;
+
+// Optional per-launch extras: the learned guess and the interface-state
+// logger (records rho_L, u_L, p_L, rho_R, u_R, p_R, p*, jump strength along
+// the sweep's normal direction).
+struct Extras {
+  const MlpDev* mlp;
+  float* log;                      // [log_cap][8] or NULL
+  unsigned long long* log_count;   // records offered so far (may exceed log_cap)
+  long long log_cap;
+  unsigned long long seed;
+  float rate_smooth;               // sampling probability of weak jumps
+  float rate_strong;               // ... of jumps with strength > 0.05
+  float gamma;
+};
+constexpr int kLogFields = 8;
 
 struct GridDesc {
   long long off;    // element offset of plane 0 in the state buffers

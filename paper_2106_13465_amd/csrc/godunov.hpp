@@ -32,6 +32,7 @@ struct Gas {
   T c_min;
   T tol;       // Newton convergence test |dp| <= tol * p
   int niter;   // Newton iteration cap
+  int niter_learned;  // cap from a learned guess before falling back
   int ipow_k;  // 1/z when it is a small integer (7 for gamma = 1.4), else 0
 };
 
@@ -90,12 +91,17 @@ struct Flux {
 };
 
 // Riemann problem at one interface: left state L, right state R.  Returns the
-// flux of the Godunov state at x/t = 0; iters/converged report the Newton
-// solve.
+// flux of the Godunov state at x/t = 0.  p_learned > 0 is a learned starting
+// guess: Newton runs at most niter_learned iterations from it, and if the
+// convergence test has not been met the solve restarts from the
+// two-rarefaction guess with the full cap (fell_back).  p_learned < 0 means a
+// learned guess was produced but is unusable (also a fall-back); 0 means no
+// learned guess.  iters counts all iterations; pstar returns the final star
+// pressure.
 template <typename T>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
-                                                const Gas<T>& G, int& iters,
-                                                bool& converged) {
+                                                const Gas<T>& G, T p_learned, int& iters,
+                                                bool& converged, bool& fell_back, T& pstar) {
   const T irL = fm::rcp(L.r), irR = fm::rcp(R.r);
   const T cL = fm::sqrt(G.g * L.p * irL);
   const T cR = fm::sqrt(G.g * R.p * irR);
@@ -106,24 +112,41 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
 
   // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), evaluated as
   // pL [num / (cL + cR (pR/pL)^-z)]^(1/z): one fractional power
-  T p;
-  const T num = cL + cR - G.half_gm1 * (R.u - L.u);
-  if (num > T(0)) {
-    const T den = cL + cR * fm::pow_pos(R.p * ipL, -G.z);
-    const T ratio = num * fm::rcp(den);
-    p = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
-  } else {
-    p = pmin;
-  }
-  p = fmax(p, pmin);
+  auto two_rarefaction = [&]() -> T {
+    T q;
+    const T num = cL + cR - G.half_gm1 * (R.u - L.u);
+    if (num > T(0)) {
+      const T den = cL + cR * fm::pow_pos(R.p * ipL, -G.z);
+      const T ratio = num * fm::rcp(den);
+      q = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
+    } else {
+      q = pmin;
+    }
+    return fmax(q, pmin);
+  };
+
+  const bool learned = p_learned > T(0);
+  T p = learned ? fmax(p_learned, pmin) : two_rarefaction();
+  int kmax = learned ? G.niter_learned : G.niter;
 
   // Newton on f(p) = sum_K (p - p_K)/W_K + u_R - u_L with the two-shock
   // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
   // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
-  int k = 0;
-  bool conv = false;
-  while (k < G.niter) {
+  int k = 0, total = 0;
+  bool conv = false, fb = false;
+  while (true) {
+    if (k >= kmax) {
+      if (learned && !fb) {  // the learned guess failed its residual test
+        fb = true;
+        p = two_rarefaction();
+        k = 0;
+        kmax = G.niter;
+        continue;
+      }
+      break;
+    }
     ++k;
+    ++total;
     const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
     const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
     const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
@@ -138,8 +161,10 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
       break;
     }
   }
-  iters = k;
+  iters = total;
   converged = conv;
+  fell_back = fb || p_learned < T(0);
+  pstar = p;
 
   // star velocity (average of the two sides' estimates) at the final p
   const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);

@@ -28,6 +28,7 @@
 #include "device_state.hpp"
 #include "godunov.hpp"
 #include "launch.hpp"
+#include "mlp.hpp"
 
 namespace hydro {
 
@@ -79,6 +80,45 @@ __device__ __forceinline__ void count_newton(DevState* st, bool valid, int key) 
   }
 }
 
+__device__ __forceinline__ void count_flag(unsigned long long* counter, bool flag) {
+  const unsigned long long m = __ballot(flag);
+  const int lane = threadIdx.x & (kWave - 1);
+  if (m != 0ull && lane == __ffsll((long long)m) - 1)
+    atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Interface-state logger: samples interfaces (stronger jumps at a higher
+// rate) into a device buffer for training the learned guess.
+template <typename T>
+__device__ __forceinline__ void log_interface(const Extras& ex, bool valid, const Prim<T>& L,
+                                              const Prim<T>& R, T pstar, unsigned long long key) {
+  if (!valid) return;
+  const float rl = (float)L.r, rr = (float)R.r, pl = (float)L.p, pr = (float)R.p;
+  const float cbar = sqrtf(ex.gamma * sqrtf(pl * pr) / sqrtf(rl * rr));
+  const float strength = fabsf(logf(pl / pr)) + fabsf((float)(R.u - L.u)) / cbar;
+  const float rate = strength > 0.05f ? ex.rate_strong : ex.rate_smooth;
+  const float u = (float)(mix64(ex.seed ^ key) >> 40) * (1.0f / 16777216.0f);
+  if (!(u < rate)) return;
+  const unsigned long long slot = atomicAdd(ex.log_count, 1ull);
+  if ((long long)slot >= ex.log_cap) return;
+  float* r = ex.log + slot * kLogFields;
+  r[0] = rl;
+  r[1] = (float)L.u;
+  r[2] = pl;
+  r[3] = rr;
+  r[4] = (float)R.u;
+  r[5] = pr;
+  r[6] = (float)pstar;
+  r[7] = strength;
+}
+
 template <typename T>
 __device__ __forceinline__ bool nonphysical(T r, T e) {
   return !(r > T(0)) || !(fabs(e) < T(INFINITY));
@@ -115,9 +155,11 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 }
 
 // ------------------------------------------------------------ x-sweep
-template <typename T, bool STATS>
-__global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G) {
+template <typename T, bool INSTR, int GUESS>
+__global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
+  MlpRegs mr;
+  if (GUESS) mlp_load(ex.mlp, mr);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -161,16 +203,24 @@ __global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G) {
 
       // Riemann problem at this lane's right interface i+1/2
       const Prim<T> qm_next = from_right(qm);
+      T p_learned = T(0);
+      if (GUESS) p_learned = mlp_guess<T>(mr, qp, qm_next, ex.gamma);
       int iters;
-      bool conv;
-      const Flux<T> F = riemann_flux(qp, qm_next, G, iters, conv);
+      bool conv, fb;
+      T pstar;
+      const Flux<T> F = riemann_flux(qp, qm_next, G, p_learned, iters, conv, fb, pstar);
       const Flux<T> Fl = from_left(F);  // interface i-1/2
 
-      if (STATS) {
+      if (INSTR) {
         // interfaces owned by this segment: x0-1/2 (first segment only) and
         // the right interfaces of its cells
         const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
         count_newton(st, valid, conv ? iters : 0);
+        if (GUESS) count_flag(&st->fallbacks, valid && fb);
+        if (ex.log)
+          log_interface(ex, valid, qp, qm_next, pstar,
+                        ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+                            ((unsigned long long)row * (d.nx + 1) + (i + 1)) * 2ull);
       }
 
       // WRITE: conservative update of cells x0 .. x0+59
@@ -206,9 +256,11 @@ __device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, co
   return d;
 }
 
-template <typename T, bool FUSE_DT, bool STATS>
-__global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G) {
+template <typename T, bool INSTR, int GUESS>
+__global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
+  MlpRegs mr;
+  if (GUESS) mlp_load(ex.mlp, mr);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -260,10 +312,21 @@ __global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G) {
       q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
       if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
       if (j >= y0 - 1) {
+        T p_learned = T(0);
+        if (GUESS) p_learned = mlp_guess<T>(mr, qp0, qm1, ex.gamma);
         int iters;
-        bool conv;
-        F = riemann_flux(qp0, qm1, G, iters, conv);
-        if (STATS) count_newton(st, xin && (j >= y0 || y0 == 0), conv ? iters : 0);
+        bool conv, fb;
+        T pstar;
+        F = riemann_flux(qp0, qm1, G, p_learned, iters, conv, fb, pstar);
+        if (INSTR) {
+          const bool valid = xin && (j >= y0 || y0 == 0);
+          count_newton(st, valid, conv ? iters : 0);
+          if (GUESS) count_flag(&st->fallbacks, valid && fb);
+          if (ex.log)
+            log_interface(ex, valid, qp0, qm1, pstar,
+                          ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+                              (((unsigned long long)x * (d.ny + 1) + (j + 1)) * 2ull + 1ull));
+        }
       }
       if (j >= y0) {
         const T nr = c0.r + lam * (Fm.m - F.m);
@@ -277,17 +340,15 @@ __global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G) {
           out[2 * P + off] = nn;
           out[3 * P + off] = ne;
           status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-          if (FUSE_DT) smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
+          smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
         }
       }
       qp0 = qp1;
       Fm = F;
     }
     if (status) atomicOr(&st->status, status);
-    if (FUSE_DT) {
-      smax = wave_max(smax);
-      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
-    }
+    smax = wave_max(smax);
+    if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
   }
 }
 
@@ -434,30 +495,37 @@ static inline unsigned blocks_for(long long items, unsigned max_blocks) {
 }
 
 template <typename T>
-hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, bool stats, unsigned max_blocks,
-                          hipStream_t s) {
+hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                          int guess, unsigned max_blocks, hipStream_t s) {
   const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
-  if (stats)
-    hipLaunchKernelGGL((k_sweep_x<T, true>), grid, block, 0, s, b, G);
-  else
-    hipLaunchKernelGGL((k_sweep_x<T, false>), grid, block, 0, s, b, G);
+  if (guess) {
+    if (instr)
+      hipLaunchKernelGGL((k_sweep_x<T, true, 1>), grid, block, 0, s, b, G, ex);
+    else
+      hipLaunchKernelGGL((k_sweep_x<T, false, 1>), grid, block, 0, s, b, G, ex);
+  } else {
+    if (instr)
+      hipLaunchKernelGGL((k_sweep_x<T, true, 0>), grid, block, 0, s, b, G, ex);
+    else
+      hipLaunchKernelGGL((k_sweep_x<T, false, 0>), grid, block, 0, s, b, G, ex);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, bool fuse_dt, bool stats,
-                          unsigned max_blocks, hipStream_t s) {
+hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                          int guess, unsigned max_blocks, hipStream_t s) {
   const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
-  if (fuse_dt) {
-    if (stats)
-      hipLaunchKernelGGL((k_sweep_y<T, true, true>), grid, block, 0, s, b, G);
+  if (guess) {
+    if (instr)
+      hipLaunchKernelGGL((k_sweep_y<T, true, 1>), grid, block, 0, s, b, G, ex);
     else
-      hipLaunchKernelGGL((k_sweep_y<T, true, false>), grid, block, 0, s, b, G);
+      hipLaunchKernelGGL((k_sweep_y<T, false, 1>), grid, block, 0, s, b, G, ex);
   } else {
-    if (stats)
-      hipLaunchKernelGGL((k_sweep_y<T, false, true>), grid, block, 0, s, b, G);
+    if (instr)
+      hipLaunchKernelGGL((k_sweep_y<T, true, 0>), grid, block, 0, s, b, G, ex);
     else
-      hipLaunchKernelGGL((k_sweep_y<T, false, false>), grid, block, 0, s, b, G);
+      hipLaunchKernelGGL((k_sweep_y<T, false, 0>), grid, block, 0, s, b, G, ex);
   }
   return hipGetLastError();
 }
@@ -507,10 +575,10 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
 }
 
 #define HYDRO_INSTANTIATE(T)                                                                   \
-  template hipError_t launch_sweep_x<T>(const Batch<T>&, const Gas<T>&, bool, unsigned,       \
-                                        hipStream_t);                                         \
-  template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, bool, bool, unsigned, \
-                                        hipStream_t);                                         \
+  template hipError_t launch_sweep_x<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
+                                        int, unsigned, hipStream_t);                          \
+  template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
+                                        int, unsigned, hipStream_t);                          \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
   template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);

@@ -9,12 +9,15 @@
 
 namespace hydro {
 
+// instr: Newton statistics and (if ex.log) the interface logger; guess: 1 =
+// learned starting guess from ex.mlp.  The y-sweep always fuses the max wave
+// speed of its output into st[].acc.
 template <typename T>
-hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, bool stats, unsigned max_blocks,
-                          hipStream_t s);
+hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                          int guess, unsigned max_blocks, hipStream_t s);
 template <typename T>
-hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, bool fuse_dt, bool stats,
-                          unsigned max_blocks, hipStream_t s);
+hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                          int guess, unsigned max_blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_max_speed(const Batch<T>& b, const Gas<T>& G, hipStream_t s);
 template <typename T>

@@ -34,6 +34,7 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
   G.tol = T(o.tol > tol_floor ? o.tol : tol_floor);
   G.niter = o.niter;
+  G.niter_learned = o.niter < 4 ? o.niter : 4;
   // 1/z = 2 gamma / (gamma - 1); an integer exponent (7 for gamma = 1.4) lets
   // the guess use repeated squaring instead of exp2/log2
   const double k = std::nearbyint(1.0 / z);
@@ -112,6 +113,7 @@ Plan::~Plan() {
   if (st) (void)hipFree(st);
   if (d_desc) (void)hipFree(d_desc);
   if (partials) (void)hipFree(partials);
+  if (log_count) (void)hipFree(log_count);
   if (V) (void)hipFree(V);
   for (auto& m : marks) {
     (void)hipEventDestroy(m.a);
@@ -158,6 +160,8 @@ hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_
   HIP_TRY(hipMalloc((void**)&st, sizeof(DevState) * n));
   HIP_TRY(hipMalloc((void**)&d_desc, sizeof(GridDesc) * n));
   HIP_TRY(hipMalloc((void**)&partials, sizeof(double) * 4 * tot_blocks));
+  HIP_TRY(hipMalloc((void**)&log_count, sizeof(unsigned long long)));
+  HIP_TRY(hipMemset(log_count, 0, sizeof(unsigned long long)));
   HIP_TRY(hipMemset(st, 0, sizeof(DevState) * n));
   return hipDeviceSynchronize();
 }
@@ -245,21 +249,50 @@ hipError_t Plan::enqueue_finalize(bool advance, bool reset) {
 }
 
 hipError_t Plan::enqueue_sweep(int dir, bool fuse_dt, const void* src, void* dst) {
-  const bool stats = opt.stats != 0;
+  (void)fuse_dt;  // the y-sweep always fuses the max wave speed
+  Extras ex;
+  ex.mlp = mlp;
+  ex.log = log;
+  ex.log_count = log_count;
+  ex.log_cap = log_cap;
+  ex.seed = log_seed;
+  ex.rate_smooth = rate_smooth;
+  ex.rate_strong = rate_strong;
+  ex.gamma = (float)gamma;
+  const bool instr = opt.stats != 0 || log != nullptr;
+  const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
   if (dtype == HYDRO_F64) {
     const Gas<double> G = make_gas<double>(gamma, opt);
     if (dir == HYDRO_DIR_X)
-      return launch_sweep_x<double>(batch_of<double>(*this, src, dst, cfg.seg_x, items_x), G,
-                                    stats, cfg.blocks_x, stream);
-    return launch_sweep_y<double>(batch_of<double>(*this, src, dst, cfg.seg_y, items_y), G,
-                                  fuse_dt, stats, cfg.blocks_y, stream);
+      return launch_sweep_x<double>(batch_of<double>(*this, src, dst, cfg.seg_x, items_x), G, ex,
+                                    instr, guess, cfg.blocks_x, stream);
+    return launch_sweep_y<double>(batch_of<double>(*this, src, dst, cfg.seg_y, items_y), G, ex,
+                                  instr, guess, cfg.blocks_y, stream);
   }
   const Gas<float> G = make_gas<float>(gamma, opt);
   if (dir == HYDRO_DIR_X)
-    return launch_sweep_x<float>(batch_of<float>(*this, src, dst, cfg.seg_x, items_x), G, stats,
-                                 cfg.blocks_x, stream);
-  return launch_sweep_y<float>(batch_of<float>(*this, src, dst, cfg.seg_y, items_y), G, fuse_dt,
-                               stats, cfg.blocks_y, stream);
+    return launch_sweep_x<float>(batch_of<float>(*this, src, dst, cfg.seg_x, items_x), G, ex,
+                                 instr, guess, cfg.blocks_x, stream);
+  return launch_sweep_y<float>(batch_of<float>(*this, src, dst, cfg.seg_y, items_y), G, ex, instr,
+                               guess, cfg.blocks_y, stream);
+}
+
+hipError_t Plan::set_logger(float* buf, long long cap, unsigned long long seed, double r_smooth,
+                            double r_strong) {
+  log = buf;
+  log_cap = buf ? cap : 0;
+  log_seed = seed;
+  rate_smooth = (float)r_smooth;
+  rate_strong = (float)r_strong;
+  drop_graph();
+  HIP_TRY(hipMemsetAsync(log_count, 0, sizeof(unsigned long long), stream));
+  return hipStreamSynchronize(stream);
+}
+
+hipError_t Plan::logger_count(unsigned long long* out) {
+  HIP_TRY(hipMemcpyAsync(out, log_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         stream));
+  return hipStreamSynchronize(stream);
 }
 
 hipError_t Plan::enqueue_step() {

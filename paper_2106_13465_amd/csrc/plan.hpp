@@ -61,6 +61,13 @@ struct Plan {
   // captured multi-step graph
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0;
+  // learned guess (borrowed device network) and interface logger
+  const MlpDev* mlp = nullptr;
+  float* log = nullptr;
+  long long log_cap = 0;
+  unsigned long long* log_count = nullptr;  // device counter (owned)
+  unsigned long long log_seed = 0;
+  float rate_smooth = 0.f, rate_strong = 0.f;
 
   ~Plan();
 
@@ -70,6 +77,9 @@ struct Plan {
   hipError_t bind(void* U_, const long* pitches, const long long* offsets, int dtype_,
                   hipStream_t s);
   hipError_t set_options(const hydro_options_t& o);
+  hipError_t set_logger(float* buf, long long cap, unsigned long long seed, double r_smooth,
+                        double r_strong);
+  hipError_t logger_count(unsigned long long* out);
   hipError_t upload_descriptors();  // after a change of geometry or launch shape
   void drop_graph();
 

@@ -172,6 +172,26 @@ class Hydro:
         check(self.lib.hydro_autotune(self.handle, ctypes.byref(t), int(use_cache)))
         return _tune_dict(t)
 
+    def set_mlp(self, net) -> None:
+        """Attach a packed network (``mlp.GuessNetwork``) or detach it (None)."""
+        self._net = net
+        ptr = ctypes.c_void_p(net.dev.data_ptr()) if net is not None else None
+        check(self.lib.hydro_set_mlp(self.handle, ptr))
+
+    def set_logger(self, records: torch.Tensor | None, seed: int = 0, rate_smooth: float = 0.01,
+                   rate_strong: float = 1.0) -> None:
+        """Log sampled interface states into records (float32 [capacity, 8])."""
+        self._log = records
+        ptr = ctypes.c_void_p(records.data_ptr()) if records is not None else None
+        cap = records.shape[0] if records is not None else 0
+        check(self.lib.hydro_set_logger(self.handle, ptr, cap, seed, rate_smooth, rate_strong))
+
+    def logger_count(self) -> int:
+        c = self.lib.hydro_logger_count(self.handle)
+        if c < 0:
+            raise HydroError(int(c), _lib.last_error())
+        return c
+
 
 def _stats_dict(s) -> dict:
     return {"interfaces": s.interfaces, "hist": list(s.hist), "fallbacks": s.fallbacks}
@@ -308,6 +328,25 @@ class HydroBatch:
 
     def set_profiling(self, enable: bool = True) -> None:
         check(self.lib.hydro_batch_set_profiling(self.handle, int(enable)))
+
+    def set_mlp(self, net) -> None:
+        self._net = net
+        ptr = ctypes.c_void_p(net.dev.data_ptr()) if net is not None else None
+        check(self.lib.hydro_batch_set_mlp(self.handle, ptr))
+
+    def set_logger(self, records: torch.Tensor | None, seed: int = 0, rate_smooth: float = 0.01,
+                   rate_strong: float = 1.0) -> None:
+        self._log = records
+        ptr = ctypes.c_void_p(records.data_ptr()) if records is not None else None
+        cap = records.shape[0] if records is not None else 0
+        check(self.lib.hydro_batch_set_logger(self.handle, ptr, cap, seed, rate_smooth,
+                                              rate_strong))
+
+    def logger_count(self) -> int:
+        c = self.lib.hydro_batch_logger_count(self.handle)
+        if c < 0:
+            raise HydroError(int(c), _lib.last_error())
+        return c
 
     def profile(self, reset: bool = True) -> dict:
         ms = (ctypes.c_double * _lib.HYDRO_NPHASES)()

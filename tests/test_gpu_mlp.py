@@ -1,0 +1,206 @@
+"""Learned star-pressure guess on the GPU: the network kernels against the
+BF16-emulating FP64 oracle, Adam, training, the interface logger, and sweeps
+with the learned guess (which must reach the same converged solution as the
+two-rarefaction path, and fall back to it when the network is unusable)."""
+import numpy as np
+import pytest
+
+from paper_2106_13465_amd import inputs
+from test_gpu_parity import TOL64, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rand_params(seed, scale=0.3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.normal(size=1313) * scale).astype(np.float32)
+
+
+def riemann_records(orc, n, seed):
+    """Random interface states with the oracle's converged two-shock p*."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rec = np.zeros((n, 8))
+    for i in range(n):
+        rL, rR, pL, pR = np.exp(rng.uniform(np.log(0.05), np.log(2.0), 4))
+        uL, uR = rng.uniform(-1.5, 1.5, 2)
+        _, ps, _, _, _ = orc.riemann([rL, uL, 0, pL], [rR, uR, 0, pR], 1.4, 30, 1e-12)
+        rec[i, :7] = (rL, uL, pL, rR, uR, pR, ps)
+    return rec
+
+
+def test_forward_matches_emulating_oracle(torch_cuda, orc):
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    P = rand_params(1)
+    net = GuessNetwork(P)
+    X = np.random.Generator(np.random.PCG64(2)).normal(size=(1000, 6)).astype(np.float32)
+    y = net.forward(torch_cuda.tensor(X, device="cuda")).cpu().numpy()
+    yo = orc.mlp_forward(P.astype(np.float64), X.astype(np.float64), emulate=True)
+    err = np.abs(y - yo) / (1 + np.abs(yo))
+    print("forward max err", err.max(), "median", np.median(err))
+    # FP32 sums in a different order may move an activation across a BF16
+    # rounding boundary (one BF16 ulp, 2^-8 relative, in one of 32 inputs)
+    assert np.median(err) < 1e-6
+    assert err.max() < 2e-3
+
+
+def test_gradient_matches_emulating_oracle(torch_cuda, orc):
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    P = rand_params(3)
+    net = GuessNetwork(P)
+    rng = np.random.Generator(np.random.PCG64(4))
+    n = 1000  # four blocks of 256 samples, the last one ragged
+    X = rng.normal(size=(n, 6)).astype(np.float32)
+    T = rng.normal(size=n).astype(np.float32)
+    g, L = net.loss_grad(torch_cuda.tensor(X, device="cuda"), torch_cuda.tensor(T, device="cuda"))
+    g = g.cpu().numpy().astype(np.float64)
+    go, Lo = orc.mlp_loss_grad(P.astype(np.float64), X.astype(np.float64),
+                               T.astype(np.float64), emulate=True)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print("grad rel err", rel, "loss", L, Lo)
+    assert abs(L - Lo) <= 1e-4 * Lo
+    assert rel < 1e-3
+    # each parameter block separately (a transposed or misplaced block would
+    # show up here even if the total norm were dominated by another block)
+    for a, b in [(0, 192), (192, 224), (224, 1248), (1248, 1280), (1280, 1312), (1312, 1313)]:
+        nb = np.linalg.norm(go[a:b])
+        assert np.linalg.norm(g[a:b] - go[a:b]) <= 2e-3 * nb + 1e-9, (a, b)
+
+
+def test_features_match_oracle(torch_cuda, orc):
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    rec = riemann_records(orc, 300, 5).astype(np.float32)
+    net = GuessNetwork(rand_params(6))
+    X, Y = net.features(torch_cuda.tensor(rec, device="cuda"))
+    X, Y = X.cpu().numpy(), Y.cpu().numpy()
+    for i in range(len(rec)):
+        x, t = orc.mlp_features(rec[i].astype(np.float64))
+        np.testing.assert_allclose(X[i], x, atol=2e-5)
+        assert abs(Y[i] - t) < 2e-5
+
+
+def test_adam_step(torch_cuda):
+    """One Adam step against the update rule written out in numpy."""
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    P = rand_params(7)
+    net = GuessNetwork(P)
+    g = np.random.Generator(np.random.PCG64(8)).normal(size=1313).astype(np.float32)
+    net.grad.copy_(torch_cuda.tensor(g, device="cuda"))
+    net.adam(lr=1e-2)
+    m = 0.1 * g
+    v = 0.001 * g * g
+    ref = P - 1e-2 * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+    np.testing.assert_allclose(net.params_numpy(), ref, rtol=1e-5, atol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def trained(torch_cuda, orc):
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    rec = riemann_records(orc, 20000, 9).astype(np.float32)
+    net = GuessNetwork(seed=0)
+    X, Y = net.features(torch_cuda.tensor(rec, device="cuda"))
+    _, loss0 = net.loss_grad(X, Y.clamp(-8, 8))
+    hist = net.train(X, Y, epochs=40, batch=256, lr=2e-3)
+    print("untrained loss", loss0, "training loss per epoch", hist)
+    return net, [loss0] + hist
+
+
+def test_training_reduces_loss(trained, torch_cuda, orc):
+    net, hist = trained
+    assert hist[-1] < 0.05 * hist[0]
+    # held-out interfaces: the guess is within a few percent of p*
+    rec = riemann_records(orc, 2000, 99).astype(np.float32)
+    X, Y = net.features(torch_cuda.tensor(rec, device="cuda"))
+    keep = (Y.abs() < 8).cpu().numpy()
+    err = (net.forward(X) - Y).abs().cpu().numpy()[keep]
+    print("held-out |ln guess - ln p*|: median", np.median(err), "p90", np.percentile(err, 90))
+    assert np.median(err) < 0.1
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, dtype_name):
+    net, _ = trained
+    from paper_2106_13465_amd.hydro import Hydro
+
+    dtype = torch_cuda.float64 if dtype_name == "f64" else torch_cuda.float32
+    U = inputs.random_states(150, 90, seed=10, rough=0.6)
+    a = Hydro(150, 90, 1.4, 0.8, 3, dtype=dtype)
+    a.set_state(U)
+    b = Hydro(150, 90, 1.4, 0.8, 3, dtype=dtype)
+    b.set_state(U)
+    b.set_mlp(net)
+    b.set_options(guess=1, stats=1)
+    a.set_options(stats=1)
+    a.step(4)
+    b.step(4)
+    sa, sb = a.stats(), b.stats()
+    print(dtype_name, "plain", sa["hist"][:8], "learned", sb["hist"][:8], "fallbacks",
+          sb["fallbacks"])
+    ga, gb = a.get_state(), b.get_state()
+    if dtype_name == "f64":
+        assert rel_err(gb, ga) <= TOL64
+        ref = U.copy()
+        for _ in range(4):
+            orc.step(ref, orc.cfg(bc=3))
+        assert rel_err(gb, ref) <= TOL64
+    else:
+        for k in range(4):
+            assert np.abs(gb[k] - ga[k]).sum() / np.abs(ga[k]).sum() < 1e-5
+    assert sb["fallbacks"] < 0.25 * sb["interfaces"]
+
+
+def test_invalid_network_falls_back(torch_cuda, orc):
+    from paper_2106_13465_amd.hydro import Hydro
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    P = rand_params(11)
+    P[5] = np.nan
+    net = GuessNetwork(P)
+    U = inputs.random_states(100, 70, seed=12, rough=0.6)
+    h = Hydro(100, 70, 1.4, 0.8, 2)
+    h.set_state(U)
+    h.set_mlp(net)
+    h.set_options(guess=1, stats=1)
+    h.step(2)
+    s = h.stats()
+    assert s["fallbacks"] == s["interfaces"] > 0
+    ref = U.copy()
+    for _ in range(2):
+        orc.step(ref, orc.cfg(bc=2))
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
+def test_logger_records(torch_cuda, orc):
+    from paper_2106_13465_amd.hydro import Hydro
+
+    U = inputs.random_states(64, 48, seed=13, rough=0.5)
+    h = Hydro(64, 48, 1.4, 0.8, 3)
+    h.set_state(U)
+    cap = 20000
+    buf = torch_cuda.zeros((cap, 8), dtype=torch_cuda.float32, device="cuda")
+    h.set_logger(buf, seed=1, rate_smooth=1.0, rate_strong=1.0)
+    h.step(1)
+    n = h.logger_count()
+    assert n == (64 + 1) * 48 + (48 + 1) * 64  # every interface of both sweeps
+    rec = buf[:n].cpu().numpy().astype(np.float64)
+    # p* of a logged interface is the two-shock root for its (FP32) states
+    for r in rec[::97]:
+        _, ps, _, _, _ = orc.riemann([r[0], r[1], 0, r[2]], [r[3], r[4], 0, r[5]], 1.4, 10, 1e-8)
+        assert abs(ps - r[6]) <= 1e-6 * ps
+    h.set_logger(buf, seed=1, rate_smooth=0.1, rate_strong=0.1)
+    h.step(2)
+    m = h.logger_count()
+    assert 0.05 * 2 * n < m < 0.2 * 2 * n
+    h.set_logger(None)
