@@ -275,6 +275,173 @@ def bench_batch(args) -> dict:
     return line
 
 
+def _iter_stats(obj):
+    s = obj.stats(reset=True)
+    hist = s["hist"]
+    conv = sum(hist[1:])
+    return {"interfaces": s["interfaces"], "unconverged": hist[0], "fallbacks": s["fallbacks"],
+            "mean_iterations": sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1),
+            "fallback_rate": s["fallbacks"] / max(s["interfaces"], 1)}
+
+
+def _timed_steps(obj, steps, graph=False):
+    import torch
+
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(obj.stream)
+    if graph:
+        obj.graph_steps(steps)
+    else:
+        obj.step(steps)
+    b.record(obj.stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_learned(args) -> dict:
+    """Learned Riemann guess: log interface states from the corner-blast and
+    Fourier+blasts runs, train the network on the GPU, then compare it with the
+    two-rarefaction guess (iterations, time, results) on the 4096^2 shear
+    layer and on the 64-grid quadrant batch; the batch is also run in plain
+    FP64 for the speedup of learned + batched FP32 over the plain FP64 path."""
+    import numpy as np
+    import torch
+
+    from paper_2106_13465_amd import inputs
+    from paper_2106_13465_amd.hydro import Hydro, HydroBatch
+    from paper_2106_13465_amd._lib import HYDRO_LEARNED_GATE_DEFAULT as GATE_DEFAULT
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    out = {}
+    cap = args.train_records
+    records = torch.zeros((cap, 8), dtype=torch.float32, device="cuda:0")
+    # --- logging: corner blast 128^2 FP64 (100 steps), Fourier+blasts 8192^2 FP32
+    print("# logging interface states", file=sys.stderr, flush=True)
+    h = Hydro(128, 128, 1.4, 0.8, "reflect", dtype=torch.float64, device="cuda:0")
+    h.set_state(inputs.blast_corner(128))
+    h.set_logger(records, seed=11, rate_smooth=0.05, rate_strong=1.0)
+    h.step(100)
+    n1 = min(h.logger_count(), cap)
+    h.set_logger(None)
+    h.close()
+    U2 = inputs.fourier_blasts(8192)
+    h = Hydro(8192, 8192, 1.4, 0.8, "periodic", dtype=torch.float32, device="cuda:0")
+    h.set_state(U2)
+    del U2
+    h.set_logger(records[n1:], seed=12, rate_smooth=0.004, rate_strong=1.0)
+    h.step(12)
+    n2 = min(h.logger_count(), cap - n1)
+    h.set_logger(None)
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    n = n1 + n2
+    out["training_data"] = {"records": n, "from_blast_corner_128": n1,
+                            "from_fourier_blasts_8192": n2}
+    # --- training
+    print(f"# training on {n} records", file=sys.stderr, flush=True)
+    net = GuessNetwork(seed=0, device="cuda:0")
+    X, Y = net.features(records[:n])
+    del records
+    t0 = time.perf_counter()
+    hist = net.train(X, Y, epochs=args.train_epochs, batch=8192, lr=1e-3, seed=1)
+    train_s = time.perf_counter() - t0
+    keep = Y.abs() < 8
+    err = (net.forward(X) - Y).abs()[keep].float()
+    out["training"] = {"epochs": args.train_epochs, "batch": 8192, "lr": 1e-3,
+                       "loss_per_epoch": hist, "seconds": train_s,
+                       "median_abs_ln_error": float(err.median().item()),
+                       "p90_abs_ln_error": float(torch.quantile(err[:1_000_000], 0.9).item())}
+    del X, Y, err, keep
+    torch.cuda.empty_cache()
+
+    # --- shear layer 4096^2 FP32: two-rarefaction vs learned guess
+    print("# shear layer 4096^2 FP32", file=sys.stderr, flush=True)
+    U3 = inputs.shear_layer(4096)
+    steps = 200 if not args.steps_given else args.steps
+    res = {}
+    finals = {}
+    for guess, gate in (("two_rarefaction", 0.0), ("learned", GATE_DEFAULT),
+                        ("learned_everywhere", 0.0)):
+        h = Hydro(4096, 4096, 1.4, 0.8, "periodic", dtype=torch.float32, device="cuda:0")
+        h.set_state(U3)
+        if guess != "two_rarefaction":
+            h.set_mlp(net)
+            h.set_options(guess=1, learned_gate=gate)
+        h.autotune(use_cache=True)
+        h.step(args.warmup)
+        h.set_profiling(True)
+        h.profile(reset=True)
+        ms = _timed_steps(h, steps)
+        prof = h.profile(reset=True)
+        h.set_profiling(False)
+        h.set_options(stats=1)
+        h.stats(reset=True)
+        h.step(1)
+        it = _iter_stats(h)
+        res[guess] = {"ms_per_step": ms, "cell_updates_per_s": 2 * 4096 * 4096 / (ms * 1e-3),
+                      "sweep_x_ms": prof["sweep_x"]["ms"] / max(prof["sweep_x"]["launches"], 1),
+                      "sweep_y_ms": prof["sweep_y"]["ms"] / max(prof["sweep_y"]["launches"], 1),
+                      "newton": it}
+        finals[guess] = h.get_state()
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    b = finals["two_rarefaction"].astype(np.float64)
+    for name in ("learned", "learned_everywhere"):
+        a = finals[name].astype(np.float64)
+        res[name]["rel_l1_vs_two_rarefaction"] = [
+            float(np.abs(a[k] - b[k]).sum() / max(np.abs(b[k]).sum(), 1e-300)) for k in range(4)]
+        res[name]["speedup_vs_two_rarefaction"] = (res["two_rarefaction"]["ms_per_step"] /
+                                                   res[name]["ms_per_step"])
+    res["learned_gate"] = GATE_DEFAULT
+    out["shear_layer_4096_f32"] = res
+    del U3, finals
+    # --- quadrant batch: plain FP64 vs FP32 two-rarefaction vs FP32 learned (graph steps)
+    print("# quadrant batch", file=sys.stderr, flush=True)
+    grids = inputs.quadrant_batch()
+    shapes = [(U.shape[2], U.shape[1]) for U in grids]
+    cells = sum(a_ * b_ for a_, b_ in shapes)
+    qsteps = 50 if not args.steps_given else args.steps
+    qres = {}
+    qfinal = {}
+    for name, dtype, guess, gate in (
+            ("plain_f64", torch.float64, 0, 0.0), ("f32_two_rarefaction", torch.float32, 0, 0.0),
+            ("f32_learned", torch.float32, 1, GATE_DEFAULT),
+            ("f32_learned_everywhere", torch.float32, 1, 0.0)):
+        bt = HydroBatch(shapes, 1.4, 0.8, "outflow", dtype=dtype, device="cuda:0")
+        bt.set_states(grids)
+        if guess:
+            bt.set_mlp(net)
+            bt.set_options(guess=1, learned_gate=gate)
+        bt.autotune(use_cache=True)
+        bt.graph_steps(qsteps)  # warm-up, captures the graph
+        bt.set_states(grids)
+        ms = _timed_steps(bt, qsteps, graph=True)
+        qfinal[name] = bt.get_states()
+        bt.set_options(stats=1)
+        bt.stats(reset=True)
+        bt.step(1)
+        qres[name] = {"ms_per_step": ms, "cell_updates_per_s": 2 * cells / (ms * 1e-3),
+                      "newton": _iter_stats(bt)}
+        bt.close()
+        del bt
+        torch.cuda.empty_cache()
+    for name in ("f32_two_rarefaction", "f32_learned", "f32_learned_everywhere"):
+        num = sum(np.abs(x.astype(np.float64)[0] - y[0]).sum()
+                  for x, y in zip(qfinal[name], qfinal["plain_f64"]))
+        den = sum(np.abs(y[0]).sum() for y in qfinal["plain_f64"])
+        qres[name]["rel_l1_density_vs_plain_f64"] = float(num / den)
+        qres[name]["speedup_vs_plain_f64"] = (qres["plain_f64"]["ms_per_step"] /
+                                              qres[name]["ms_per_step"])
+    qres["cells"] = cells
+    qres["steps"] = qsteps
+    out["quadrant_batch_64"] = qres
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,7 +450,9 @@ def main() -> int:
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--workload", default="fourier_blasts",
                     choices=["fourier_blasts", "shear_layer", "blast_corner", "multiblast_batch",
-                             "quadrant_batch"])
+                             "quadrant_batch", "learned"])
+    ap.add_argument("--train-records", type=int, default=10_000_000)
+    ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 variant")
@@ -305,6 +474,10 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args)), flush=True)
+        return 0
 
     if args.workload in BATCH_WORKLOADS:
         if args.dtype == "f64" and not args.dtype_given:

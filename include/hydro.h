@@ -67,8 +67,11 @@ enum {
 
 #define HYDRO_MAX_NITER 32
 
+#define HYDRO_LEARNED_GATE_DEFAULT 1.0
+
 /* Solver options (hydro_set_options).  Defaults: niter 10, tol 1e-8,
- * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library. */
+ * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library,
+ * learned_gate HYDRO_LEARNED_GATE_DEFAULT. */
 typedef struct {
   int niter;     /* Newton iteration cap, 1..HYDRO_MAX_NITER              */
   double tol;    /* convergence test |dp| <= tol * p, > 0                  */
@@ -77,6 +80,13 @@ typedef struct {
   int seg_x;     /* x-sweep: consecutive 60-cell wave segments per wave;
                     0 = library default                                    */
   int seg_y;     /* y-sweep: cells per marching thread; 0 = default        */
+  double learned_gate; /* with HYDRO_GUESS_MLP: strength s above which an
+                    interface takes the learned guess; the others keep the
+                    two-rarefaction guess, and a wave evaluates the network
+                    only when one of its interfaces is above.  An interface
+                    is above when max(pL,pR) > e^s min(pL,pR) or
+                    (uR-uL)^2 (rhoL+rhoR) > s^2 gamma (pL+pR).  s <= 0: every
+                    interface takes the learned guess.  Finite, <= 50.     */
 } hydro_options_t;
 
 /* Riemann-solver statistics accumulated since the last reset

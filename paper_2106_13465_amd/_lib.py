@@ -35,7 +35,11 @@ class hydro_options_t(ctypes.Structure):
         ("stats", ctypes.c_int),
         ("seg_x", ctypes.c_int),
         ("seg_y", ctypes.c_int),
+        ("learned_gate", ctypes.c_double),
     ]
+
+
+HYDRO_LEARNED_GATE_DEFAULT = 1.0
 
 
 class hydro_stats_t(ctypes.Structure):

@@ -104,6 +104,8 @@ int check_options(const hydro::Plan* p, const hydro_options_t* o) {
     return fail(HYDRO_ESTATE, "learned guess requested but no network set (hydro_set_mlp)");
   if (o->seg_x < 0 || o->seg_x > 4096) return fail(HYDRO_EINVAL, "seg_x %d", o->seg_x);
   if (o->seg_y < 0 || o->seg_y > (1 << 20)) return fail(HYDRO_EINVAL, "seg_y %d", o->seg_y);
+  if (!std::isfinite(o->learned_gate) || o->learned_gate > 50.0)
+    return fail(HYDRO_EINVAL, "learned_gate %g: must be finite and <= 50", o->learned_gate);
   return HYDRO_OK;
 }
 

@@ -52,6 +52,8 @@ struct Extras {
   float rate_smooth;               // sampling probability of weak jumps
   float rate_strong;               // ... of jumps with strength > 0.05
   float gamma;
+  float gate_kappa;                // learned guess where pmax > kappa pmin (0: everywhere)
+  float gate_theta2;               // ... or du^2 (rL+rR) > theta2 gamma (pL+pR)
 };
 constexpr int kLogFields = 8;
 

@@ -155,11 +155,28 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 }
 
 // ------------------------------------------------------------ x-sweep
+// Waves per SIMD the register allocator must leave room for, per sweep
+// variant (1: no constraint).  Values above what the variant needs on its own
+// trade spills of loop-invariant values for occupancy.  Timed on MI355X over
+// an 8192^2 state: the FP64 y-sweep runs 1.47 -> 1.21 ms at 3 waves instead
+// of 2, the FP32 y-sweep 0.69 -> 0.62 ms at 6 instead of 5, the FP32 sweeps
+// with the learned guess 1.09 -> 0.92 ms (x, 6 waves) and 0.75 -> 0.67 ms
+// (y, 5); asking for more (FP64 x at 5, FP32 at 8) spills inside the Newton
+// loop and runs 1.3-2.5x slower.
+#ifndef HYDRO_OCC
+#define HYDRO_OCC 1, 1, 1, 6, 3, 1, 6, 5
+#endif
+constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 learned, then y
+template <typename T, int GUESS>
+struct SweepOcc {
+  static constexpr int v = (sizeof(T) == 8 ? 0 : 2) + (GUESS ? 1 : 0);
+  static constexpr int x = kOcc[v];
+  static constexpr int y = kOcc[4 + v];
+};
+
 template <typename T, bool INSTR, int GUESS>
-__global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
-  MlpRegs mr;
-  if (GUESS) mlp_load(ex.mlp, mr);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -204,7 +221,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex
       // Riemann problem at this lane's right interface i+1/2
       const Prim<T> qm_next = from_right(qm);
       T p_learned = T(0);
-      if (GUESS) p_learned = mlp_guess<T>(mr, qp, qm_next, ex.gamma);
+      if (GUESS)
+        p_learned = learned_guess<T>(ex.mlp, qp, qm_next, ex.gamma, ex.gate_kappa, ex.gate_theta2);
       int iters;
       bool conv, fb;
       T pstar;
@@ -257,10 +275,8 @@ __device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, co
 }
 
 template <typename T, bool INSTR, int GUESS>
-__global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
-  MlpRegs mr;
-  if (GUESS) mlp_load(ex.mlp, mr);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -313,7 +329,8 @@ __global__ __launch_bounds__(256) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex
       if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
       if (j >= y0 - 1) {
         T p_learned = T(0);
-        if (GUESS) p_learned = mlp_guess<T>(mr, qp0, qm1, ex.gamma);
+        if (GUESS)
+          p_learned = learned_guess<T>(ex.mlp, qp0, qm1, ex.gamma, ex.gate_kappa, ex.gate_theta2);
         int iters;
         bool conv, fb;
         T pstar;

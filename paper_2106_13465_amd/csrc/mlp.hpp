@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "godunov.hpp"
 
 namespace hydro {
@@ -199,17 +201,94 @@ __device__ __forceinline__ float mlp_forward(const MlpRegs& r, const float x[6],
   return y;
 }
 
-// Learned starting guess for the Riemann problem of this lane (whole wave).
-// Returns a non-positive value when the network is invalid or the output is
-// not a finite positive pressure.
+// Inference inside the sweeps: the same arithmetic as mlp_forward<false>,
+// one 16-sample tile at a time.  Each tile re-reads its weight fragments
+// (6 KB, cache-resident) through one wave-uniform base and three lane
+// offsets, so the branch that evaluates the network keeps few registers live
+// next to the sweep's own state.  Must be called by all 64 lanes.
+__device__ __forceinline__ float mlp_infer(const MlpDev* __restrict__ m, const float x[6]) {
+  const int l = threadIdx.x & 63, g = l >> 4, col = l & 15;
+  const char* base = reinterpret_cast<const char*>(m);
+  float y = 0.0f;
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    unsigned ow1 = (unsigned)(offsetof(MlpDev, w1) + col * 32 + g * 8);   // w1[col][4g]
+    unsigned ow2 = (unsigned)(offsetof(MlpDev, w2p) + col * 64 + g * 16); // w2p[col][8g]
+    unsigned ov = (unsigned)(g * 16);                                    // b1/b2/w3[4g]
+    // opaque to the optimiser: the loads below stay in the tile loop rather
+    // than being hoisted and held across all four tiles
+    __asm__("" : "+v"(ow1), "+v"(ow2), "+v"(ov));
+    const int src = 16 * t + col;
+    float v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = __shfl(x[k], src);
+    mlp_v4s b1op;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float f = g == 0 ? v[e] : (g == 1 && e < 2 ? v[4 + e] : 0.0f);
+      b1op[e] = (short)bf16_bits(f);
+    }
+    mlp_v8bf b2op;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const mlp_v4s w1 = *reinterpret_cast<const mlp_v4s*>(base + ow1 + mt * 16 * 32);
+      const mlp_v4f b1 =
+          *reinterpret_cast<const mlp_v4f*>(base + offsetof(MlpDev, b1) + ov + mt * 64);
+      mlp_v4f c = {0.f, 0.f, 0.f, 0.f};
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1, b1op, c, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        b2op[4 * mt + e] = __builtin_bit_cast(__bf16, bf16_bits(fmaxf(c[e] + b1[e], 0.0f)));
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const mlp_v8bf w2 = *reinterpret_cast<const mlp_v8bf*>(base + ow2 + mt * 16 * 64);
+      const mlp_v4f b2 =
+          *reinterpret_cast<const mlp_v4f*>(base + offsetof(MlpDev, b2) + ov + mt * 64);
+      const mlp_v4f w3 =
+          *reinterpret_cast<const mlp_v4f*>(base + offsetof(MlpDev, w3) + ov + mt * 64);
+      mlp_v4f c = {0.f, 0.f, 0.f, 0.f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2, b2op, c, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s = fmaf(w3[e], fmaxf(c[e] + b2[e], 0.0f), s);
+    }
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (g == t) y = s;
+  }
+  return y + m->b3;
+}
+
+// Strength test of the learned guess: a pressure jump above the factor kappa
+// or a velocity jump of the order of theta times the sound speed.  kappa = 0
+// selects every interface.
 template <typename T>
-__device__ __forceinline__ T mlp_guess(const MlpRegs& r, const Prim<T>& L, const Prim<T>& R,
-                                       float gamma) {
+__device__ __forceinline__ bool learned_wanted(const Prim<T>& L, const Prim<T>& R, float gamma,
+                                               float kappa, float theta2) {
+  if (!(kappa > 0.0f)) return true;
+  const float pl = (float)L.p, pr = (float)R.p;
+  const float du = (float)(R.u - L.u);
+  return fmaxf(pl, pr) > kappa * fminf(pl, pr) ||
+         du * du * ((float)L.r + (float)R.r) > theta2 * gamma * (pl + pr);
+}
+
+// Starting guess of this lane's Riemann problem: 0 when the strength test
+// keeps the two-rarefaction guess, the network's p* otherwise, or -1 when the
+// network is invalid or its output is not a finite positive pressure.  A wave
+// evaluates the network only if one of its lanes passes the test (the branch
+// is wave-uniform).  Must be called by all 64 lanes.
+template <typename T>
+__device__ __forceinline__ T learned_guess(const MlpDev* m, const Prim<T>& L, const Prim<T>& R,
+                                          float gamma, float kappa, float theta2) {
+  const bool want = learned_wanted(L, R, gamma, kappa, theta2);
+  if (__ballot(want) == 0ull) return T(0);
   float x[6], lpbar;
   mlp_features(L, R, gamma, x, lpbar);
-  const float y = mlp_forward<false>(r, x, nullptr);
+  const float y = mlp_infer(m, x);
   const float p = fm::exp2((y + lpbar) * 1.4426950408889634f);
-  return (r.valid && p > 0.0f && p < INFINITY) ? T(p) : T(-1);
+  if (!want) return T(0);
+  return (m->valid && p > 0.0f && p < INFINITY) ? T(p) : T(-1);
 }
 
 }  // namespace hydro

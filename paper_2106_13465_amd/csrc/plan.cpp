@@ -135,6 +135,7 @@ hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_
   opt.niter = 10;
   opt.tol = 1e-8;
   opt.guess = HYDRO_GUESS_PTR;
+  opt.learned_gate = HYDRO_LEARNED_GATE_DEFAULT;
   HIP_TRY(hipGetDevice(&device));
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
@@ -259,6 +260,10 @@ hipError_t Plan::enqueue_sweep(int dir, bool fuse_dt, const void* src, void* dst
   ex.rate_smooth = rate_smooth;
   ex.rate_strong = rate_strong;
   ex.gamma = (float)gamma;
+  // strength test of the learned guess: pmax > kappa pmin or du^2 (rL+rR) > theta2 gamma (pL+pR);
+  // kappa = 0 passes every interface
+  ex.gate_kappa = opt.learned_gate > 0.0 ? (float)std::exp(opt.learned_gate) : 0.0f;
+  ex.gate_theta2 = opt.learned_gate > 0.0 ? (float)(opt.learned_gate * opt.learned_gate) : 0.0f;
   const bool instr = opt.stats != 0 || log != nullptr;
   const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
   if (dtype == HYDRO_F64) {

@@ -175,6 +175,8 @@ class Hydro:
     def set_mlp(self, net) -> None:
         """Attach a packed network (``mlp.GuessNetwork``) or detach it (None)."""
         self._net = net
+        if net is not None:
+            self.stream.wait_stream(net.stream)  # the packed weights are ready
         ptr = ctypes.c_void_p(net.dev.data_ptr()) if net is not None else None
         check(self.lib.hydro_set_mlp(self.handle, ptr))
 
@@ -282,7 +284,8 @@ class HydroBatch:
         return [self.view(g).detach().to("cpu").numpy().copy() for g in range(self.n)]
 
     def set_options(self, **kw) -> None:
-        o = _lib.hydro_options_t(niter=10, tol=1e-8, guess=0, stats=0, seg_x=0, seg_y=0)
+        o = _lib.hydro_options_t(niter=10, tol=1e-8, guess=0, stats=0, seg_x=0, seg_y=0,
+                                learned_gate=_lib.HYDRO_LEARNED_GATE_DEFAULT)
         for k, v in getattr(self, "_opts", {}).items():
             setattr(o, k, v)
         for k, v in kw.items():
@@ -331,6 +334,8 @@ class HydroBatch:
 
     def set_mlp(self, net) -> None:
         self._net = net
+        if net is not None:
+            self.stream.wait_stream(net.stream)
         ptr = ctypes.c_void_p(net.dev.data_ptr()) if net is not None else None
         check(self.lib.hydro_batch_set_mlp(self.handle, ptr))
 

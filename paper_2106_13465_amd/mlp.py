@@ -67,7 +67,16 @@ class GuessNetwork:
     def _s(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
 
+    # The kernels run on self.stream; inputs come from, and outputs go back to,
+    # torch's current stream, so both directions are ordered explicitly.
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def pack(self) -> None:
+        self._enter()
         check(self.lib.hydro_mlp_pack(_ptr(self.params), _ptr(self.dev), self._s()))
 
     def set_params(self, p) -> None:
@@ -80,13 +89,17 @@ class GuessNetwork:
         n = records.shape[0]
         X = torch.empty((n, N_IN), dtype=torch.float32, device=self.device)
         Y = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._enter()
         check(self.lib.hydro_mlp_features(_ptr(records), n, gamma, _ptr(X), _ptr(Y), self._s()))
+        self._leave()
         return X, Y
 
     def forward(self, X: torch.Tensor) -> torch.Tensor:
         n = X.shape[0]
         Y = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._enter()
         check(self.lib.hydro_mlp_forward(_ptr(self.dev), _ptr(X), _ptr(Y), n, self._s()))
+        self._leave()
         return Y
 
     def loss_grad(self, X: torch.Tensor, T: torch.Tensor):
@@ -95,6 +108,7 @@ class GuessNetwork:
         need = self.lib.hydro_mlp_grad_scratch_bytes(n) // 4
         if self._scratch is None or self._scratch.numel() < need:
             self._scratch = torch.empty(need, dtype=torch.float32, device=self.device)
+        self._enter()
         check(self.lib.hydro_mlp_grad(_ptr(self.dev), _ptr(X), _ptr(T), n, _ptr(self._scratch),
                                       _ptr(self.grad), _ptr(self.loss), self._s()))
         self.stream.synchronize()
@@ -102,6 +116,7 @@ class GuessNetwork:
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
         self.step_count += 1
+        self._enter()
         check(self.lib.hydro_mlp_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v),
                                       _ptr(self.grad), self.step_count, lr, beta1, beta2, eps,
                                       self._s()))
@@ -111,6 +126,7 @@ class GuessNetwork:
         """Mini-batch Adam on the device; returns the mean loss of each epoch."""
         n = X.shape[0]
         batch = min(batch, n)
+        self._enter()
         with torch.cuda.stream(self.stream):
             T = T.clamp(-TARGET_CLIP, TARGET_CLIP)
         g = torch.Generator(device=self.device)

@@ -129,8 +129,9 @@ def test_training_reduces_loss(trained, torch_cuda, orc):
     assert np.median(err) < 0.1
 
 
+@pytest.mark.parametrize("gate", [0.0, 1.0])
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
-def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, dtype_name):
+def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, dtype_name, gate):
     net, _ = trained
     from paper_2106_13465_amd.hydro import Hydro
 
@@ -141,7 +142,7 @@ def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, d
     b = Hydro(150, 90, 1.4, 0.8, 3, dtype=dtype)
     b.set_state(U)
     b.set_mlp(net)
-    b.set_options(guess=1, stats=1)
+    b.set_options(guess=1, stats=1, learned_gate=gate)
     a.set_options(stats=1)
     a.step(4)
     b.step(4)
@@ -161,6 +162,28 @@ def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, d
     assert sb["fallbacks"] < 0.25 * sb["interfaces"]
 
 
+def test_gate_above_every_jump_is_the_plain_path(torch_cuda, trained):
+    """A gate no interface passes: no wave evaluates the network, every
+    interface starts from the two-rarefaction guess as in the plain path."""
+    net, _ = trained
+    from paper_2106_13465_amd.hydro import Hydro
+
+    U = inputs.random_states(130, 70, seed=14, rough=0.6)
+    a = Hydro(130, 70, 1.4, 0.8, 3)
+    a.set_state(U)
+    b = Hydro(130, 70, 1.4, 0.8, 3)
+    b.set_state(U)
+    b.set_mlp(net)
+    b.set_options(guess=1, stats=1, learned_gate=50.0)
+    a.set_options(stats=1)
+    a.step(3)
+    b.step(3)
+    sa, sb = a.stats(), b.stats()
+    assert sb["hist"] == sa["hist"]
+    assert sb["fallbacks"] == 0
+    assert rel_err(b.get_state(), a.get_state()) <= 1e-14
+
+
 def test_invalid_network_falls_back(torch_cuda, orc):
     from paper_2106_13465_amd.hydro import Hydro
     from paper_2106_13465_amd.mlp import GuessNetwork
@@ -172,7 +195,7 @@ def test_invalid_network_falls_back(torch_cuda, orc):
     h = Hydro(100, 70, 1.4, 0.8, 2)
     h.set_state(U)
     h.set_mlp(net)
-    h.set_options(guess=1, stats=1)
+    h.set_options(guess=1, stats=1, learned_gate=0.0)  # every interface asks the network
     h.step(2)
     s = h.stats()
     assert s["fallbacks"] == s["interfaces"] > 0

@@ -217,6 +217,11 @@ def test_error_paths(torch_cuda):
     with pytest.raises(HydroError):
         g.set_options(tol=-1.0)
     with pytest.raises(HydroError):
+        g.set_options(learned_gate=float("nan"))
+    with pytest.raises(HydroError):
+        g.set_options(learned_gate=51.0)
+    assert g.options()["learned_gate"] == _lib.HYDRO_LEARNED_GATE_DEFAULT
+    with pytest.raises(HydroError):
         g.graph_steps(0)
     # a non-finite state is latched and reported at the next synchronising call
     U = inputs.uniform(16, 16)
