@@ -26,9 +26,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s per split step & HBM GB/s vs peak; learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_fourier_blasts_8192_pmc.json")
+# rocprofv3 counter summaries (HBM bytes per launch), one per workload
+PMC_SUMMARY = {"fourier_blasts": "sweep_fourier_blasts_8192_pmc.json",
+               "multiblast_batch": "sweep_multiblast_batch_256_pmc.json",
+               "quadrant_batch": "sweep_quadrant_batch_64_pmc.json"}
 KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/godunov.hpp",
-                  "paper_2106_13465_amd/csrc/fastmath.hpp", "paper_2106_13465_amd/csrc/device_state.hpp"]
+                  "paper_2106_13465_amd/csrc/fastmath.hpp", "paper_2106_13465_amd/csrc/device_state.hpp",
+                  "paper_2106_13465_amd/csrc/mlp.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -111,11 +115,12 @@ def sweep_record(cells, elem, phase):
             "algorithmic_bytes": alg_bytes, "hbm_gbps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def pmc_traffic(kernel: str, dtype_name: str):
+def pmc_traffic(workload_name: str, kernel: str, dtype_name: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if missing or taken from different kernel sources."""
+    summary of the workload, or None if missing or taken from different kernel
+    sources."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(os.path.join(ROOT, "profiles", PMC_SUMMARY[workload_name])) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -250,7 +255,7 @@ def bench_batch(args) -> dict:
         "newton": newton,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
-                     "traffic": pmc_traffic(dom_name + "_batch", args.dtype),
+                     "traffic": pmc_traffic(args.workload, dom_name, args.dtype),
                      "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
                      "avg_launch_ms": dom["avg_ms"]},
         "per_grid_loop": {"ms_per_step": loop_ms, "speedup_of_batched_graph": loop_ms / ms_step},
@@ -527,7 +532,7 @@ def main() -> int:
     res = results[main_dn]
     sx, sy = res["sweeps"]["x"], res["sweeps"]["y"]
     dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
-    traffic = pmc_traffic(dom_name, main_dn)
+    traffic = pmc_traffic(args.workload, dom_name, main_dn)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
                 "traffic": traffic, "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],

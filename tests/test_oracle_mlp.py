@@ -77,3 +77,72 @@ def test_emulated_forward_close_to_exact(orc):
     y = orc.mlp_forward(P, X, emulate=False)
     assert np.max(np.abs(ye - y)) < 0.05 * (1 + np.max(np.abs(y)))
     assert np.max(np.abs(ye - y)) > 0  # rounding is applied
+
+
+def _routing_params():
+    """Hand-built network whose output has a closed form: units 0-5 of layer 1
+    pass x_k, units 6-11 pass -x_k; layer 2 permutes the units (unit i reads
+    unit perm[i]); layer 3 weighs unit i by (i + 1) / 8."""
+    P = np.zeros(1313)
+    for k in range(6):
+        P[0 + k * 6 + k] = 1.0          # W1[k][k]
+        P[0 + (6 + k) * 6 + k] = -1.0   # W1[6+k][k]
+    perm = [(5 * i + 3) % 32 for i in range(32)]
+    for i in range(32):
+        P[224 + i * 32 + perm[i]] = 1.0  # W2[i][perm[i]]
+        P[1280 + i] = (i + 1) / 8.0      # W3[i]
+    P[1312] = 0.25                       # b3
+    return P, perm
+
+
+def test_forward_closed_form(orc):
+    """Routing network: y = b3 + sum_i w3_i relu(a1[perm[i]]) with
+    a1 = (relu(x), relu(-x), 0, ...), evaluated unit by unit."""
+    P, perm = _routing_params()
+    rng = np.random.Generator(np.random.PCG64(7))
+    X = np.round(rng.normal(size=(40, 6)) * 8) / 8  # exactly representable in BF16
+    for emulate in (False, True):
+        y = orc.mlp_forward(P, X, emulate=emulate)
+        for x, yv in zip(X, y):
+            a1 = [max(v, 0.0) for v in x] + [max(-v, 0.0) for v in x] + [0.0] * 20
+            expect = 0.25 + sum((i + 1) / 8.0 * a1[perm[i]] for i in range(32))
+            assert yv == expect, (x, yv, expect)
+
+
+def test_emulated_gradient_exact_when_representable(orc):
+    """With weights, inputs and residuals that BF16 holds exactly, the
+    emulated gradient equals the exact one (itself pinned by finite
+    differences), so the emulation only rounds, it does not reroute."""
+    P, _ = _routing_params()
+    P[192:224] = 0.125  # b1
+    rng = np.random.Generator(np.random.PCG64(8))
+    X = np.round(rng.normal(size=(4, 6)) * 4) / 4
+    y = orc.mlp_forward(P, X, emulate=False)
+    T = y - np.array([0.5, -0.25, 1.0, 0.125])  # residuals y - t
+    ge, Le = orc.mlp_loss_grad(P, X, T, emulate=True)
+    g, L = orc.mlp_loss_grad(P, X, T, emulate=False)
+    assert Le == L
+    np.testing.assert_array_equal(ge, g)
+    assert np.count_nonzero(g[224:1248]) > 0 and np.count_nonzero(g[0:192]) > 0
+
+
+def test_emulated_error_signals_are_bf16(orc):
+    """In the emulated backward pass the error signals entering a matrix
+    product are BF16 values: with x_0 = 1 and a layer-1 unit that passes x_0
+    (so a1 = 1 there), the W2 column of that unit holds bf16(dL/dz2) and the
+    first W1 column holds bf16(dL/dz1)."""
+    import oracle
+
+    P = rand_params(9, 0.4)
+    P[0:6] = [1.0, 0, 0, 0, 0, 0]  # W1[0] passes x_0
+    P[192] = 0.0                   # b1[0]
+    rng = np.random.Generator(np.random.PCG64(10))
+    for trial in range(20):
+        X = np.concatenate([[1.0], np.round(rng.normal(size=5) * 16) / 16]).reshape(1, 6)
+        T = rng.normal(size=1)
+        g, _ = orc.mlp_loss_grad(P, X, T, emulate=True)
+        col_w2 = g[224:1248].reshape(32, 32)[:, 0]  # dL/dW2[i][0] = bf16(gz2_i) * a1[0]
+        col_w1 = g[0:192].reshape(32, 6)[:, 0]      # dL/dW1[k][0] = bf16(gz1_k) * 1
+        for v in np.concatenate([col_w2, col_w1]):
+            assert oracle.mlp_bf16(v) == v, (trial, v)
+        assert np.count_nonzero(col_w2) > 0 and np.count_nonzero(col_w1) > 0
