@@ -444,6 +444,63 @@ def bench_learned(args) -> dict:
     qres["cells"] = cells
     qres["steps"] = qsteps
     out["quadrant_batch_64"] = qres
+
+    # --- strong jumps: a network trained on logs of such grids, first step of a fresh grid
+    for fname, fam in (("strong_jumps_p2", dict(p_decades=2.0, rho_decades=1.0, speed=2.0)),
+                       ("strong_jumps_p4", dict(p_decades=4.0, rho_decades=2.0, speed=3.0))):
+        print(f"# {fname}", file=sys.stderr, flush=True)
+        rec = torch.zeros((2_200_000, 8), dtype=torch.float32, device="cuda:0")
+        h = Hydro(1024, 1024, 1.4, 0.8, "periodic", dtype=torch.float64, device="cuda:0")
+        h.set_state(inputs.strong_jumps(1024, 1024, 31, **fam))
+        h.set_logger(rec, seed=7, rate_smooth=1.0, rate_strong=1.0)
+        h.step(1)
+        n = min(h.logger_count(), rec.shape[0])
+        h.set_logger(None)
+        h.close()
+        net_s = GuessNetwork(seed=0, device="cuda:0")
+        X, Y = net_s.features(rec[:n])
+        del rec
+        hist = net_s.train(X, Y, epochs=20, batch=2048, lr=2e-3, seed=1)
+        err = (net_s.forward(X) - Y).abs()[Y.abs() < 8].float()
+        sres = {"family": fam, "grid": "4096^2, periodic, first step of a fresh seed",
+                "training": {"records": n, "epochs": 20, "batch": 2048, "lr": 2e-3,
+                             "loss_first_last": [hist[0], hist[-1]],
+                             "median_abs_ln_error": float(err.median().item())}}
+        del X, Y, err
+        U4 = inputs.strong_jumps(4096, 4096, 32, **fam)
+        for dn, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            for name, guess, gate in (("two_rarefaction", 0, 0.0), ("learned", 1, GATE_DEFAULT),
+                                      ("learned_everywhere", 1, 0.0)):
+                h = Hydro(4096, 4096, 1.4, 0.8, "periodic", dtype=dt, device="cuda:0")
+                if guess:
+                    h.set_mlp(net_s)
+                h.set_options(guess=guess, learned_gate=gate, stats=1)
+                h.set_state(U4)
+                h.step(1)
+                it = _iter_stats(h)
+                h.set_options(stats=0)
+                h.set_profiling(True)
+                xs, ys = [], []
+                for _ in range(3):
+                    h.set_state(U4)
+                    h.profile(reset=True)
+                    h.step(1)
+                    pr = h.profile(reset=True)
+                    xs.append(pr["sweep_x"]["ms"])
+                    ys.append(pr["sweep_y"]["ms"])
+                h.close()
+                del h
+                sres[f"{dn}_{name}"] = {"newton": it, "sweep_x_ms": min(xs), "sweep_y_ms": min(ys)}
+            base = sres[f"{dn}_two_rarefaction"]
+            for name in ("learned", "learned_everywhere"):
+                r = sres[f"{dn}_{name}"]
+                r["iteration_ratio_vs_two_rarefaction"] = (
+                    r["newton"]["mean_iterations"] / base["newton"]["mean_iterations"])
+                r["sweep_time_ratio_vs_two_rarefaction"] = (
+                    (r["sweep_x_ms"] + r["sweep_y_ms"]) / (base["sweep_x_ms"] + base["sweep_y_ms"]))
+        del U4
+        torch.cuda.empty_cache()
+        out[fname] = sres
     return out
 
 

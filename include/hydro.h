@@ -198,7 +198,7 @@ int hydro_get_profile(hydro_t *h, double ms[HYDRO_NPHASES], long long launches[H
  * method; the two-rarefaction guess with the full Newton cap stays the
  * fallback).  A 6 -> 32 -> 32 -> 1 network with ReLU activations, BF16 weights
  * and activations on the MFMA units, FP32 accumulation.  Features of an
- * interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar), w = (u_L-u_bar)/c_bar,
+ * interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar), w = asinh((u_L-u_bar)/c_bar),
  * x = (a, b, w, -a, -b, -w) with geometric means rho_bar, p_bar, u_bar the
  * mean velocity and c_bar = sqrt(gamma p_bar/rho_bar); output
  * y ~ ln(p_star / p_bar).  In a sweep with options.guess = HYDRO_GUESS_MLP, Newton

@@ -15,7 +15,8 @@
  * for W1's gradient).  Everything else, including every sum, is FP64.
  *
  * Features of an interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar),
- * w = (u_L - u_bar)/c_bar, x = (a, b, w, -a, -b, -w), target ln(p_star / p_bar),
+ * w = asinh((u_L - u_bar)/c_bar), x = (a, b, w, -a, -b, -w),
+ * target ln(p_star / p_bar),
  * with rho_bar, p_bar geometric means, u_bar the mean velocity and
  * c_bar = sqrt(gamma p_bar / rho_bar).
  */
@@ -120,9 +121,9 @@ void mlp_oracle_features(const double *rec, double gamma, double *x, double *tar
   const double cbar = sqrt(gamma * pbar / rbar);
   x[0] = log(rec[0] / rbar);
   x[1] = log(rec[2] / pbar);
-  x[2] = (rec[1] - ubar) / cbar;
+  x[2] = asinh((rec[1] - ubar) / cbar);
   x[3] = log(rec[3] / rbar);
   x[4] = log(rec[5] / pbar);
-  x[5] = (rec[4] - ubar) / cbar;
+  x[5] = asinh((rec[4] - ubar) / cbar);
   if (target) *target = log(rec[6] / pbar);
 }

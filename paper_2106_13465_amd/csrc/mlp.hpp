@@ -3,11 +3,12 @@
 // FP32 accumulation.  One wave evaluates 64 samples (one per lane).
 //
 // Features of an interface (all dimensionless, FP32):
-//   a = ln(rho_L / rho_bar), b = ln(p_L / p_bar), w = (u_L - u_bar) / c_bar
+//   a = ln(rho_L / rho_bar), b = ln(p_L / p_bar), w = asinh((u_L - u_bar) / c_bar)
 //   x = (a, b, w, -a, -b, -w)
 // with rho_bar = sqrt(rho_L rho_R), p_bar = sqrt(p_L p_R), u_bar = (u_L+u_R)/2,
 // c_bar = sqrt(gamma p_bar / rho_bar); the second triple is the right
-// state's (ln rho_R/rho_bar = -a, ...).  Target y = ln(p* / p_bar); guess
+// state's (ln rho_R/rho_bar = -a, ...).  asinh keeps strong velocity jumps
+// (|u_L - u_R| >> c_bar) on the logarithmic scale of the other two features.  Target y = ln(p* / p_bar); guess
 // p_bar exp(y).
 //
 // Network (W row-major [out][in]; bf16() rounds to nearest even):
@@ -103,6 +104,16 @@ __device__ __forceinline__ void mlp_load(const MlpDev* m, MlpRegs& r) {
   r.valid = m->valid;
 }
 
+// asinh in FP32: odd Taylor polynomial below 1/16 (truncation < 3e-9
+// relative), ln(|w| + sqrt(w^2 + 1)) above, |w| capped at 1e18.
+__device__ __forceinline__ float mlp_asinh(float w) {
+  const float a = fminf(fabsf(w), 1e18f);
+  const float a2 = a * a;
+  const float small = a * (1.0f + a2 * (-1.0f / 6.0f + a2 * (3.0f / 40.0f)));
+  const float large = fm::log2(a + fm::sqrt(a2 + 1.0f)) * 0.69314718055994531f;
+  return copysignf(a < 0.0625f ? small : large, w);
+}
+
 // Features of one interface (FP32) and ln(p_bar).
 template <typename T>
 __device__ __forceinline__ void mlp_features(const Prim<T>& L, const Prim<T>& R, float gamma,
@@ -114,7 +125,7 @@ __device__ __forceinline__ void mlp_features(const Prim<T>& L, const Prim<T>& R,
   const float b = 0.5f * (l2pl - l2pr) * ln2;
   // c_bar = sqrt(gamma p_bar / rho_bar) = 2^(0.5 log2 gamma + 0.25 (log2 pL pR - log2 rL rR))
   const float l2c = 0.5f * fm::log2(gamma) + 0.25f * ((l2pl + l2pr) - (l2rl + l2rr));
-  const float w = 0.5f * ((float)L.u - (float)R.u) * fm::exp2(-l2c);
+  const float w = mlp_asinh(0.5f * ((float)L.u - (float)R.u) * fm::exp2(-l2c));
   x[0] = a;
   x[1] = b;
   x[2] = w;

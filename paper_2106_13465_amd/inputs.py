@@ -99,6 +99,22 @@ def random_states(nx: int, ny: int, seed: int, gamma=GAMMA, rough: float = 1.0) 
     return conservative(rho, u, v, p, gamma)
 
 
+def strong_jumps(nx: int, ny: int, seed: int, gamma=GAMMA, p_decades: float = 4.0,
+                 rho_decades: float = 2.0, speed: float = 3.0) -> np.ndarray:
+    """Cell-wise independent random states with strong jumps: rho log-uniform
+    over rho_decades, p log-uniform over p_decades (both centred on 1),
+    velocities uniform in [-speed, speed].  Most interfaces carry a strong
+    shock or rarefaction, the regime where the two-rarefaction guess is
+    poor."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ln10 = np.log(10.0)
+    rho = np.exp(rng.uniform(-0.5, 0.5, size=(ny, nx)) * rho_decades * ln10)
+    p = np.exp(rng.uniform(-0.5, 0.5, size=(ny, nx)) * p_decades * ln10)
+    u = rng.uniform(-speed, speed, size=(ny, nx))
+    v = rng.uniform(-speed, speed, size=(ny, nx))
+    return conservative(rho, u, v, p, gamma)
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------
