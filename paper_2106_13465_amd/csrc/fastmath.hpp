@@ -2,11 +2,16 @@
 // on gfx950, built on the hardware approximations (v_rcp, v_rsq, v_log,
 // v_exp) instead of the libm-style sequences.
 //
-// FP64: v_rcp_f64 / v_rsq_f64 followed by two Newton-Raphson steps (error
-//   about one ulp for positive normal arguments, which is all the sweep
-//   passes: densities and pressures are floored far above the denormal
-//   range).  log2/exp2 are short polynomials accurate to ~1e-14; they only
-//   feed the two-rarefaction starting guess, which Newton corrects.
+// FP64: v_rcp_f64 / v_rsq_f64 (relative error below 2^-24) followed by one
+//   third-order correction: with e the residual of the hardware estimate,
+//   1/x = r (1 + e + e^2 + ...) and 1/sqrt(x) = r (1 + e/2 + 3e^2/8 + ...),
+//   truncated after e^2, which leaves a truncation error below 2^-72 and the
+//   rounding of the last operations (about one ulp) for the positive normal
+//   arguments the sweep passes (densities and pressures are floored far above
+//   the denormal range).  sqrt(x) = x * (1/sqrt(x)).  log2/exp2 are short
+//   polynomials accurate to ~1e-14; root_inv gives x^(-1/k) from an FP32
+//   seed and one Newton step.  They only feed the two-rarefaction starting
+//   guess, which Newton corrects.
 // FP32: the single hardware instructions (about one ulp).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -16,39 +21,22 @@ namespace fm {
 
 // ---------------------------------------------------------------- reciprocal
 __device__ __forceinline__ double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);  // 1 - x r
+  return fma(r, fma(e, e, e), r);    // r (1 + e + e^2)
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------- 1/sqrt
 __device__ __forceinline__ double rsqrt(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  double e = fma(-hx * r, r, 0.5);
-  r = fma(r, e, r);
-  e = fma(-hx * r, r, 0.5);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x, r * r, 1.0);                // 1 - x r^2
+  return fma(r * e, fma(e, 0.375, 0.5), r);            // r (1 + e/2 + 3e^2/8)
 }
 __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // ---------------------------------------------------------------- sqrt
-__device__ __forceinline__ double sqrt(double x) {
-  // g = x r, h = r/2 refined together (Goldschmidt form)
-  const double r0 = __builtin_amdgcn_rsq(x);
-  double g = x * r0;
-  double h = 0.5 * r0;
-  double e = fma(-g, h, 0.5);
-  g = fma(g, e, g);
-  h = fma(h, e, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
-  return fma(d, h, g);
-}
+__device__ __forceinline__ double sqrt(double x) { return x * rsqrt(x); }
 __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ---------------------------------------------------------------- log2 / exp2
@@ -113,6 +101,23 @@ __device__ __forceinline__ T ipow(T x, int k) {
     k >>= 1;
   }
   return r;
+}
+
+// x^(-1/k) for a small positive integer k (uniform across the wave) and
+// positive x, inv_k = 1/k: an FP32 seed 2^(-log2(x)/k) from the hardware
+// log2/exp2 (relative error ~1e-7), then one Newton step on x y^k = 1,
+// y <- y (1 - (x y^k - 1)/k), which squares the error (~k 1e-14).  x outside
+// the FP32 normal range takes the FP64 polynomial path.
+__device__ __forceinline__ double root_inv(double x, int k, double inv_k) {
+  if (!(x > 0x1p-120 && x < 0x1p120)) return exp2(-inv_k * log2(x));
+  const float lx = __builtin_amdgcn_logf((float)x);
+  const double y0 = (double)__builtin_amdgcn_exp2f(-lx * (float)inv_k);
+  const double t = fma(x, ipow(y0, k), -1.0);
+  return fma(-y0 * inv_k, t, y0);
+}
+__device__ __forceinline__ float root_inv(float x, int k, float inv_k) {
+  (void)k;
+  return exp2(-inv_k * log2(x));
 }
 
 }  // namespace fm

@@ -56,10 +56,10 @@ __device__ __forceinline__ Prim<T> cons_to_prim(T U0, T Un, T Ut, T E, const Gas
   return q;
 }
 
+// minmod: the argument of smaller magnitude if both have the same sign, else 0
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
-  T m = a > T(0) ? fmin(a, b) : fmax(a, b);
-  return a * b <= T(0) ? T(0) : m;
+  return a * b > T(0) ? copysign(fmin(fabs(a), fabs(b)), a) : T(0);
 }
 
 // MUSCL-Hancock half-step trace of one cell: face states at x_{i-1/2} (qm)
@@ -102,12 +102,27 @@ template <typename T>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
                                                 const Gas<T>& G, T p_learned, int& iters,
                                                 bool& converged, bool& fell_back, T& pstar) {
-  const T irL = fm::rcp(L.r), irR = fm::rcp(R.r);
+  T irL, irR, ipL, ipR;
+  if constexpr (sizeof(T) == 8) {
+    // FP64: the four reciprocals from one, 1/(rho_L rho_R p_L p_R) (the
+    // product stays far inside the double range for floored states)
+    const T rr = L.r * R.r, pp = L.p * R.p;
+    const T inv = fm::rcp(rr * pp);
+    const T invr = inv * pp, invp = inv * rr;
+    irL = R.r * invr;
+    irR = L.r * invr;
+    ipL = R.p * invp;
+    ipR = L.p * invp;
+  } else {
+    irL = fm::rcp(L.r);
+    irR = fm::rcp(R.r);
+    ipL = fm::rcp(L.p);
+    ipR = fm::rcp(R.p);
+  }
   const T cL = fm::sqrt(G.g * L.p * irL);
   const T cR = fm::sqrt(G.g * R.p * irR);
   const T CL = G.g * L.p * L.r;  // Lagrangian sound speed squared
   const T CR = G.g * R.p * R.r;
-  const T ipL = fm::rcp(L.p), ipR = fm::rcp(R.p);
   const T pmin = fmin(L.r, R.r) * G.pfloor;
 
   // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), evaluated as
@@ -116,7 +131,8 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     T q;
     const T num = cL + cR - G.half_gm1 * (R.u - L.u);
     if (num > T(0)) {
-      const T den = cL + cR * fm::pow_pos(R.p * ipL, -G.z);
+      const T x = R.p * ipL;
+      const T den = cL + cR * (G.ipow_k > 0 ? fm::root_inv(x, G.ipow_k, G.z) : fm::pow_pos(x, -G.z));
       const T ratio = num * fm::rcp(den);
       q = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
     } else {

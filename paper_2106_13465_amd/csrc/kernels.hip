@@ -318,6 +318,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
     Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
     double smax = 0.0;
     int status = 0;
+#pragma unroll 3
     for (int j = y0 - 4; j < y1; ++j) {
       c0 = c1;
       c1 = c2;
