@@ -403,66 +403,92 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     }
   }
   if (!cached) {
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
+    constexpr int kMaxReps = 9;
+    hipEvent_t ev[kMaxReps + 1];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     const LaunchCfg saved = cfg;
     // sweeps read U and write V only; dt must be set for the kernels to run
     HIP_TRY(enqueue_max_speed());
     HIP_TRY(enqueue_finalize(false, false));
-    const unsigned persist[] = {0u, (unsigned)(cus * 2), (unsigned)(cus * 4), (unsigned)(cus * 8)};
-    auto time_it = [&](int dir, double& ms) -> hipError_t {
+    // median of `reps` launches, each timed by its own event pair, after one
+    // warm-up launch
+    auto time_it = [&](int dir, const LaunchCfg& c, int reps, double& ms) -> hipError_t {
+      cfg = c;
       HIP_TRY(upload_descriptors());
-      HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));  // warm-up
-      HIP_TRY(hipEventRecord(a, stream));
-      const int reps = 3;
-      for (int r = 0; r < reps; ++r) HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
-      HIP_TRY(hipEventRecord(b, stream));
-      HIP_TRY(hipEventSynchronize(b));
-      float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, a, b));
-      ms = t / reps;
+      HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
+      HIP_TRY(hipEventRecord(ev[0], stream));
+      for (int r = 0; r < reps; ++r) {
+        HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
+        HIP_TRY(hipEventRecord(ev[r + 1], stream));
+      }
+      HIP_TRY(hipEventSynchronize(ev[reps]));
+      float t[kMaxReps];
+      for (int r = 0; r < reps; ++r) HIP_TRY(hipEventElapsedTime(&t[r], ev[r], ev[r + 1]));
+      std::sort(t, t + reps);
+      ms = t[reps / 2];
       return hipSuccess;
     };
+    // Round 1: every candidate, 3 launches.  Round 2: the three fastest again,
+    // 9 launches each, in two interleaved passes; the lowest median wins.
+    auto tune_dir = [&](int dir, const std::vector<LaunchCfg>& cands, LaunchCfg& win,
+                        double& win_ms) -> hipError_t {
+      std::vector<std::pair<double, int>> r1;
+      for (int i = 0; i < (int)cands.size(); ++i) {
+        double ms;
+        HIP_TRY(time_it(dir, cands[i], 3, ms));
+        r1.push_back({ms, i});
+        ++tried;
+      }
+      std::sort(r1.begin(), r1.end());
+      const int top = std::min<int>(3, (int)r1.size());
+      std::vector<double> best_ms(top, 1e30);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int t = 0; t < top; ++t) {
+          double ms;
+          HIP_TRY(time_it(dir, cands[r1[t].second], kMaxReps, ms));
+          best_ms[t] = std::min(best_ms[t], ms);
+        }
+      int bi = 0;
+      for (int t = 1; t < top; ++t)
+        if (best_ms[t] < best_ms[bi]) bi = t;
+      win = cands[r1[bi].second];
+      win_ms = best_ms[bi];
+      return hipSuccess;
+    };
+    const unsigned persist[] = {0u, (unsigned)(cus * 2), (unsigned)(cus * 4), (unsigned)(cus * 8)};
     const int segx[] = {1, 2, 4, 8};
     const int segy[] = {32, 64, 128, 256, 512};
     int maxny = 0;
     for (int g = 0; g < n; ++g) maxny = std::max(maxny, ny[g]);
+    std::vector<LaunchCfg> cx, cy;
     for (int sx : segx) {
       if (user_seg_x && sx != saved.seg_x) continue;
       for (unsigned pb : persist) {
-        cfg = saved;
-        cfg.seg_x = sx;
-        cfg.blocks_x = pb;
-        double ms;
-        HIP_TRY(time_it(HYDRO_DIR_X, ms));
-        ++tried;
-        if (best_x < 0 || ms < best_x) {
-          best_x = ms;
-          best.seg_x = sx;
-          best.blocks_x = pb;
-        }
+        LaunchCfg c = saved;
+        c.seg_x = sx;
+        c.blocks_x = pb;
+        cx.push_back(c);
       }
     }
     for (int sy : segy) {
       if (user_seg_y && sy != saved.seg_y) continue;
       if (!user_seg_y && sy > 2 * maxny && sy != 32) continue;
       for (unsigned pb : persist) {
-        cfg = saved;
-        cfg.seg_y = sy;
-        cfg.blocks_y = pb;
-        double ms;
-        HIP_TRY(time_it(HYDRO_DIR_Y, ms));
-        ++tried;
-        if (best_y < 0 || ms < best_y) {
-          best_y = ms;
-          best.seg_y = sy;
-          best.blocks_y = pb;
-        }
+        LaunchCfg c = saved;
+        c.seg_y = sy;
+        c.blocks_y = pb;
+        cy.push_back(c);
       }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    LaunchCfg wx = saved, wy = saved;
+    if (!cx.empty()) HIP_TRY(tune_dir(HYDRO_DIR_X, cx, wx, best_x));
+    if (!cy.empty()) HIP_TRY(tune_dir(HYDRO_DIR_Y, cy, wy, best_y));
+    best = saved;
+    best.seg_x = wx.seg_x;
+    best.blocks_x = wx.blocks_x;
+    best.seg_y = wy.seg_y;
+    best.blocks_y = wy.blocks_y;
+    for (auto& e : ev) (void)hipEventDestroy(e);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
