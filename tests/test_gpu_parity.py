@@ -192,6 +192,35 @@ def test_graph_replay_matches_eager(torch_cuda, orc):
     assert rel_err(a.get_state(), ref) <= TOL64
 
 
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.3])
+def test_other_gamma_steps(torch_cuda, orc, gamma):
+    """gamma = 5/3 (integer exponent 2 gamma/(gamma-1) = 5 in the guess) and
+    gamma = 1.3 (non-integer exponent): 5 steps of a random state against the
+    oracle."""
+    from paper_2106_13465_amd.hydro import Hydro
+
+    U = inputs.random_states(140, 90, seed=31, gamma=gamma, rough=0.8)
+    h = Hydro(140, 90, gamma, 0.8, 2)
+    h.set_state(U)
+    h.set_options(stats=1)
+    h.step(5)
+    ref = U.copy()
+    c = orc.cfg(gamma=gamma, bc=2)
+    hist = np.zeros(11, dtype=np.int64)  # Newton cap 10
+    for _ in range(5):
+        orc.step(ref, c, hist)
+    assert rel_err(h.get_state(), ref) <= TOL64
+    s = h.stats()
+    # Newton iteration counts: the guesses differ in their last bits, so a
+    # count may differ on a few interfaces; the unconverged ones must agree
+    g = np.array(s["hist"][:11])
+    assert g[0] == hist[0]
+    assert g.sum() == hist.sum() > 0
+    gpu_mean = sum(k * v for k, v in enumerate(g)) / hist.sum()
+    orc_mean = sum(k * v for k, v in enumerate(hist)) / hist.sum()
+    assert abs(gpu_mean - orc_mean) <= 0.01 * orc_mean
+
+
 def test_error_paths(torch_cuda):
     """Invalid arguments come back as error codes with a message."""
     from paper_2106_13465_amd import _lib
