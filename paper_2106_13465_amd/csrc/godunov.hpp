@@ -200,7 +200,6 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   const T co = left ? cL : cR;
   const T Xo = left ? XL : XR;
   const T iWo = left ? iWL : iWR;
-  const T s = left ? T(1) : T(-1);
 
   // star density: 1/rho* = 1/rho_o - (p* - p_o)/W_o^2, floored
   T irs = iro + (po - p) * (iWo * iWo);
@@ -208,27 +207,23 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   const T rs = fm::rcp(irs);
   const T cs = fmax(G.c_min, fm::sqrt(G.g * p * irs));
 
-  // outer/inner edge speeds of the wave on that side, positive away from
-  // the interface
-  T sout, sin_;
-  if (p >= po) {
-    sout = Xo * iWo * iro - s * uo;  // shock: W_o / rho_o - s u_o
-    sin_ = sout;
-  } else {
-    sout = co - s * uo;
-    sin_ = cs - s * us;
-  }
+  // outer/inner edge speeds of the wave on that side, positive away from the
+  // interface (s = +1 on the left, -1 on the right): a shock moves at
+  // W_o/rho_o - s u_o, a rarefaction spans c_o - s u_o .. c* - s u*
+  const T uos = left ? L.u : -R.u;  // s u_o
+  const T uss = left ? us : -us;    // s u*
+  const T wsh = Xo * iWo * iro - uos;
+  const bool shock = p >= po;
+  const T sout = shock ? wsh : co - uos;
+  const T sin_ = shock ? wsh : cs - uss;
 
-  T gr, gu, gp;
-  if (sout < T(0)) {
-    gr = ro;
-    gu = uo;
-    gp = po;
-  } else if (sin_ > T(0)) {
-    gr = rs;
-    gu = us;
-    gp = p;
-  } else {
+  // x/t = 0 lies outside the wave (unperturbed side), inside the star
+  // region, or inside a rarefaction fan (linear across it)
+  const bool outside = sout < T(0);
+  T gr = outside ? ro : rs;
+  T gu = outside ? uo : us;
+  T gp = outside ? po : p;
+  if (!outside && !(sin_ > T(0))) {
     T f = sout * fm::rcp(fmax(sout - sin_, G.c_min));
     f = fmin(fmax(f, T(0)), T(1));
     gr = f * rs + (T(1) - f) * ro;
