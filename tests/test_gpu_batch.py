@@ -142,3 +142,41 @@ def test_batch_totals_and_fp32(torch_cuda, orc):
         tot = orc.totals(np.ascontiguousarray(G))
         A = np.abs(G).sum(axis=(1, 2)) / max(G.shape[1:]) ** 2
         assert np.all(np.abs(T[g] - tot) <= 1e-13 * A + 1e-300), g
+
+
+def test_many_tiny_grids(torch_cuda, orc):
+    """300 grids of 2..17 cells a side with all three boundary types: the work
+    list's grid search and the per-grid dt over many small entries."""
+    from paper_2106_13465_amd.hydro import HydroBatch
+
+    rng = np.random.Generator(np.random.PCG64(77))
+    shapes = [(int(rng.integers(2, 18)), int(rng.integers(2, 18))) for _ in range(300)]
+    bcs = [int(b) for b in rng.integers(1, 4, size=300)]
+    states = [inputs.random_states(nx, ny, seed=1000 + g, rough=0.6)
+              for g, (nx, ny) in enumerate(shapes)]
+    b = HydroBatch(shapes, 1.4, 0.8, bcs, dtype=torch_cuda.float64)
+    b.set_states(states)
+    b.step(3)
+    got = b.get_states()
+    for g, U in enumerate(states):
+        ref = U.copy()
+        c = orc.cfg(bc=bcs[g])
+        for _ in range(3):
+            orc.step(ref, c)
+        assert rel_err(got[g], ref) <= TOL64, (g, shapes[g], bcs[g])
+
+
+@pytest.mark.parametrize("shape", [(4096, 2), (2, 4096), (3001, 3)])
+def test_extreme_aspect_ratios(torch_cuda, orc, shape):
+    from paper_2106_13465_amd.hydro import Hydro
+
+    nx, ny = shape
+    U = inputs.random_states(nx, ny, seed=nx + ny, rough=0.6)
+    h = Hydro(nx, ny, 1.4, 0.8, "periodic", dtype=torch_cuda.float64)
+    h.set_state(U)
+    h.step(4)
+    ref = U.copy()
+    c = orc.cfg(bc=3)
+    for _ in range(4):
+        orc.step(ref, c)
+    assert rel_err(h.get_state(), ref) <= TOL64
