@@ -119,6 +119,8 @@ def pmc_traffic(workload_name: str, kernel: str, dtype_name: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of the workload, or None if missing or taken from different kernel
     sources."""
+    if workload_name not in PMC_SUMMARY:
+        return None
     try:
         with open(os.path.join(ROOT, "profiles", PMC_SUMMARY[workload_name])) as f:
             rec = json.load(f)

@@ -87,6 +87,8 @@ __device__ __forceinline__ void count_flag(unsigned long long* counter, bool fla
     atomicAdd(counter, (unsigned long long)__popcll(m));
 }
 
+// SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014): a
+// counter-based hash for the logger's sampling decisions.
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   z += 0x9e3779b97f4a7c15ull;
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;

@@ -249,8 +249,8 @@ hipError_t Plan::enqueue_finalize(bool advance, bool reset) {
   return launch_finalize_dt(d_desc, st, n, advance, reset, stream);
 }
 
-hipError_t Plan::enqueue_sweep(int dir, bool fuse_dt, const void* src, void* dst) {
-  (void)fuse_dt;  // the y-sweep always fuses the max wave speed
+hipError_t Plan::enqueue_sweep(int dir, const void* src, void* dst) {
+  // (the y-sweep always fuses the max wave speed of its output)
   Extras ex;
   ex.mlp = mlp;
   ex.log = log;
@@ -311,18 +311,18 @@ hipError_t Plan::enqueue_step() {
   }
   {
     PhaseTimer pt(this, HYDRO_PHASE_SWEEP_X);
-    HIP_TRY(enqueue_sweep(HYDRO_DIR_X, false, U, V));
+    HIP_TRY(enqueue_sweep(HYDRO_DIR_X, U, V));
   }
   {
     PhaseTimer pt(this, HYDRO_PHASE_SWEEP_Y);
-    HIP_TRY(enqueue_sweep(HYDRO_DIR_Y, true, V, U));
+    HIP_TRY(enqueue_sweep(HYDRO_DIR_Y, V, U));
   }
   acc_valid = true;
   return hipSuccess;
 }
 
 hipError_t Plan::enqueue_single_sweep(int dir) {
-  HIP_TRY(enqueue_sweep(dir, false, U, V));
+  HIP_TRY(enqueue_sweep(dir, U, V));
   acc_valid = false;
   if (dtype == HYDRO_F64) return launch_copy<double>(batch_of<double>(*this, V, U, 0, rows), stream);
   return launch_copy<float>(batch_of<float>(*this, V, U, 0, rows), stream);
@@ -415,10 +415,10 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     auto time_it = [&](int dir, const LaunchCfg& c, int reps, double& ms) -> hipError_t {
       cfg = c;
       HIP_TRY(upload_descriptors());
-      HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
+      HIP_TRY(enqueue_sweep(dir, U, V));
       HIP_TRY(hipEventRecord(ev[0], stream));
       for (int r = 0; r < reps; ++r) {
-        HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
+        HIP_TRY(enqueue_sweep(dir, U, V));
         HIP_TRY(hipEventRecord(ev[r + 1], stream));
       }
       HIP_TRY(hipEventSynchronize(ev[reps]));

@@ -85,7 +85,7 @@ struct Plan {
 
   hipError_t enqueue_max_speed();          // st[].acc <- max speed of U
   hipError_t enqueue_finalize(bool advance, bool reset);
-  hipError_t enqueue_sweep(int dir, bool fuse_dt, const void* src, void* dst);
+  hipError_t enqueue_sweep(int dir, const void* src, void* dst);
   hipError_t enqueue_step();               // dt (fused max), x-sweep U->V, y-sweep V->U
   hipError_t enqueue_single_sweep(int dir);  // U->V, copy back
   hipError_t enqueue_totals();
