@@ -511,7 +511,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--size", type=int, default=0,
+                    help="grid side (default: 8192 fourier_blasts, 4096 shear_layer, "
+                         "128 blast_corner)")
     ap.add_argument("--workload", default="fourier_blasts",
                     choices=["fourier_blasts", "shear_layer", "blast_corner", "multiblast_batch",
                              "quadrant_batch", "learned"])
@@ -549,6 +551,9 @@ def main() -> int:
         print(json.dumps(bench_batch(args)), flush=True)
         return 0
 
+    if not args.size:
+        args.size = {"fourier_blasts": 8192, "shear_layer": 4096, "blast_corner": 128}.get(
+            args.workload, 8192)
     print(f"# generating {args.workload} {args.size}^2", file=sys.stderr, flush=True)
     U, bc, desc = workload(args.workload, args.size)
     _, ny, nx = U.shape
