@@ -148,9 +148,24 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   // Newton on f(p) = sum_K (p - p_K)/W_K + u_R - u_L with the two-shock
   // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
   // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
-  int k = 0, total = 0;
-  bool conv = false, fb = false;
-  while (true) {
+  auto newton_step = [&](T& pp) -> bool {  // one iteration; true when converged
+    const T XL = CL * (T(1) + G.gs * (pp - L.p) * ipL);
+    const T XR = CR * (T(1) + G.gs * (pp - R.p) * ipR);
+    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
+    const T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
+    const T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
+    const T usL = L.u - (pp - L.p) * iWL;
+    const T usR = R.u + (pp - R.p) * iWR;
+    const T dp = (usL - usR) * fm::rcp(izL + izR);
+    pp = fmax(pp + dp, pmin);
+    return fabs(dp) <= G.tol * pp;
+  };
+  // The first iteration runs for every interface as straight-line code; the
+  // loop only carries the interfaces that need more (or fall back).
+  int k = 1, total = 1;
+  bool fb = false;
+  bool conv = newton_step(p);
+  while (!conv) {
     if (k >= kmax) {
       if (learned && !fb) {  // the learned guess failed its residual test
         fb = true;
@@ -163,19 +178,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     }
     ++k;
     ++total;
-    const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
-    const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
-    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
-    const T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
-    const T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
-    const T usL = L.u - (p - L.p) * iWL;
-    const T usR = R.u + (p - R.p) * iWR;
-    const T dp = (usL - usR) * fm::rcp(izL + izR);
-    p = fmax(p + dp, pmin);
-    if (fabs(dp) <= G.tol * p) {
-      conv = true;
-      break;
-    }
+    conv = newton_step(p);
   }
   iters = total;
   converged = conv;
