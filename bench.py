@@ -533,7 +533,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the sweep runs on a single MI355X in this build "
+        print("bench.py measures one GPU: the sweep runs on a single MI355X "
               "(multi-GPU slab decomposition is not implemented); run with --gpus 1",
               file=sys.stderr)
         return 2

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
     T ir1, ir2 = T(1);
     Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
     Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
-    double smax = 0.0;
+    T smax = T(0);  // max of T values is exact; widened once for the atomic
     int status = 0;
 #pragma unroll 3
     for (int j = y0 - 4; j < y1; ++j) {
@@ -360,15 +360,15 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
           out[2 * P + off] = nn;
           out[3 * P + off] = ne;
           status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-          smax = fmax(smax, (double)max_speed(nr, nn, nt, ne, G));
+          smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
         }
       }
       qp0 = qp1;
       Fm = F;
     }
     if (status) atomicOr(&st->status, status);
-    smax = wave_max(smax);
-    if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(smax));
+    const double wmax = wave_max((double)smax);
+    if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
   }
 }
 

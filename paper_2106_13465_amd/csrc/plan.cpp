@@ -428,7 +428,7 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
       ms = t[reps / 2];
       return hipSuccess;
     };
-    // Round 1: every candidate, 3 launches.  Round 2: the three fastest again,
+    // First pass: every candidate, 3 launches.  Second pass: the three fastest again,
     // 9 launches each, in two interleaved passes; the lowest median wins.
     auto tune_dir = [&](int dir, const std::vector<LaunchCfg>& cands, LaunchCfg& win,
                         double& win_ms) -> hipError_t {

@@ -8,9 +8,9 @@ float64 arrays of shape [4, ny, nx] (x fastest).  Cells are square with
 h = 1/max(nx, ny); cell centres sit at ((i+1/2) h, (j+1/2) h).
 
 The paper's own test case is a point-explosion problem (Section 7); the
-workloads here are synthetic stand-ins of that type and of the other flows
-named for this build (shear layers, random Riemann quadrants), generated from
-numpy's PCG64 with a fixed seed per workload.
+workloads here are synthetic stand-ins of that type and of other standard flows
+(shear layers, random Riemann quadrants, strong jumps), generated from numpy's
+PCG64 with a fixed seed per workload.
 """
 from __future__ import annotations
 
