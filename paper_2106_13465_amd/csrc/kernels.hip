@@ -535,6 +535,20 @@ hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
 }
 
 template <typename T>
+int sweep_y_blocks_per_cu(bool instr, int guess) {
+  int nb = 0;
+  const int threads = kWave * kWavesPerBlock;
+  hipError_t e;
+  if (guess)
+    e = instr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, true, 1>, threads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, false, 1>, threads, 0);
+  else
+    e = instr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, true, 0>, threads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, false, 0>, threads, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
   const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
@@ -601,6 +615,7 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
                                         int, unsigned, hipStream_t);                          \
   template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
                                         int, unsigned, hipStream_t);                          \
+  template int sweep_y_blocks_per_cu<T>(bool, int);                                           \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
   template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);

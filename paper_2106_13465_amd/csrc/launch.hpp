@@ -18,6 +18,10 @@ hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
 template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s);
+// Resident blocks per CU of the y-sweep variant (runtime occupancy query),
+// for sizing its work items to whole rounds of the chip; 0 on error.
+template <typename T>
+int sweep_y_blocks_per_cu(bool instr, int guess);
 template <typename T>
 hipError_t launch_max_speed(const Batch<T>& b, const Gas<T>& G, hipStream_t s);
 template <typename T>

@@ -457,9 +457,36 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     };
     const unsigned persist[] = {0u, (unsigned)(cus * 2), (unsigned)(cus * 4), (unsigned)(cus * 8)};
     const int segx[] = {1, 2, 4, 8};
-    const int segy[] = {32, 64, 128, 256, 512};
+    std::vector<int> segy = {32, 64, 128, 256, 512};
     int maxny = 0;
     for (int g = 0; g < n; ++g) maxny = std::max(maxny, ny[g]);
+    // Balanced segments: the shortest seg_y whose work items fit in k whole
+    // rounds of the resident waves (k = 1, 2, 3), so no round runs part-full.
+    {
+      const bool instr = opt.stats != 0 || log != nullptr;
+      const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
+      const int bpc = dtype == HYDRO_F64 ? sweep_y_blocks_per_cu<double>(instr, guess)
+                                         : sweep_y_blocks_per_cu<float>(instr, guess);
+      const long long slots = (long long)cus * bpc * kWavesPerBlock;
+      auto items_for = [&](int sy) {
+        long long it = 0;
+        for (int g = 0; g < n; ++g)
+          it += (long long)((nx[g] + kWave - 1) / kWave) * ((ny[g] + sy - 1) / sy);
+        return it;
+      };
+      for (int k = 1; k <= 3 && slots > 0; ++k) {
+        int lo = 16, hi = std::max(16, maxny);
+        if (items_for(hi) > k * slots) continue;
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if (items_for(mid) <= k * slots)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        if (std::find(segy.begin(), segy.end(), lo) == segy.end()) segy.push_back(lo);
+      }
+    }
     std::vector<LaunchCfg> cx, cy;
     for (int sx : segx) {
       if (user_seg_x && sx != saved.seg_x) continue;
