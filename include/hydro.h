@@ -176,11 +176,13 @@ int hydro_graph_steps(hydro_t *h, int nsteps);
 /* Copy the Riemann statistics (synchronises); reset clears them. */
 int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
 
-/* Time candidate launch shapes (segments per item, persistent block counts)
- * of both sweeps on the bound state and keep the fastest.  U is not
- * modified; the fused max speed is invalidated.  use_cache reuses the result
- * of an earlier tuning of the same grid shapes and dtype in this process.
- * Synchronises.  out may be NULL. */
+/* Time candidate launch shapes of both sweeps on the bound state and keep
+ * the fastest: segments per work item (for the y-sweep also lengths whose
+ * items fill whole rounds of the resident waves) times persistent block
+ * counts; the three fastest are re-timed and the lowest median wins.  U is
+ * not modified; the fused max speed is invalidated.  use_cache reuses the
+ * result of an earlier tuning of the same grid shapes and dtype in this
+ * process.  Synchronises.  out may be NULL. */
 int hydro_autotune(hydro_t *h, hydro_tune_t *out, int use_cache);
 
 /* Kernel timing.  While enabled, hydro_step records a HIP event pair on the
