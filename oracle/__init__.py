@@ -22,6 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BC_REFLECT, BC_OUTFLOW, BC_PERIODIC = 1, 2, 3
+LIMITER_MINMOD, LIMITER_MC, LIMITER_VANLEER = 0, 1, 2
+ORDER_XY, ORDER_ALTERNATE = 0, 1
 DIR_X, DIR_Y = 0, 1
 RHO_MIN = 1e-10
 C_MIN = 1e-10
@@ -34,6 +36,8 @@ class Cfg(ctypes.Structure):
         ("bc", ctypes.c_int),
         ("niter", ctypes.c_int),
         ("tol", ctypes.c_double),
+        ("limiter", ctypes.c_int),
+        ("order", ctypes.c_int),
     ]
 
 
@@ -56,6 +60,7 @@ def _load():
         "oracle_p_floor": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
         "oracle_sound_speed": (ctypes.c_double, [_D, ctypes.c_double]),
         "oracle_minmod": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
+        "oracle_limit": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_int]),
         "oracle_trace": (None, [_D, _D, ctypes.c_double, ctypes.c_double, _D, _D]),
         "oracle_ptr_guess": (ctypes.c_double, [_D, _D, ctypes.c_double]),
         "oracle_two_shock_f": (ctypes.c_double, [_D, _D, ctypes.c_double, ctypes.c_double]),
@@ -80,6 +85,9 @@ def _load():
             ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg)]),
         "oracle_step": (
             ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg), _LL]),
+        "oracle_step_n": (
+            ctypes.c_double,
+            [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg), ctypes.c_long, _LL]),
         "oracle_totals": (None, [_D, ctypes.c_int, ctypes.c_int, _D]),
         "oracle_threads": (ctypes.c_int, []),
         "mlp_oracle_nparams": (ctypes.c_int, []),
@@ -105,8 +113,10 @@ def _vec(x) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(4))
 
 
-def cfg(gamma=1.4, cfl=0.8, bc=BC_PERIODIC, niter=10, tol=1e-8) -> Cfg:
-    return Cfg(float(gamma), float(cfl), int(bc), int(niter), float(tol))
+def cfg(gamma=1.4, cfl=0.8, bc=BC_PERIODIC, niter=10, tol=1e-8, limiter=LIMITER_MINMOD,
+        order=ORDER_XY) -> Cfg:
+    return Cfg(float(gamma), float(cfl), int(bc), int(niter), float(tol), int(limiter),
+               int(order))
 
 
 # ---------------------------------------------------------------- single steps
@@ -128,6 +138,10 @@ def sound_speed(q, gamma=1.4) -> float:
 
 def minmod(a, b) -> float:
     return _load().oracle_minmod(float(a), float(b))
+
+
+def limit(a, b, limiter) -> float:
+    return _load().oracle_limit(float(a), float(b), int(limiter))
 
 
 def trace(q, dq, gamma, lam):
@@ -212,12 +226,13 @@ def compute_dt(U: np.ndarray, c: Cfg) -> float:
     return _load().oracle_compute_dt(_dptr(U), nx, ny, ctypes.byref(c))
 
 
-def step(U: np.ndarray, c: Cfg, hist: np.ndarray | None = None) -> float:
-    """In-place time step (dt, x-sweep, y-sweep); returns dt."""
+def step(U: np.ndarray, c: Cfg, hist: np.ndarray | None = None, step_index: int = 0) -> float:
+    """In-place time step (dt, then the two sweeps in the order c.order gives
+    for step number step_index); returns dt."""
     _grid(U)
     _, ny, nx = U.shape
     hp = hist.ctypes.data_as(_LL) if hist is not None else None
-    return _load().oracle_step(_dptr(U), nx, ny, ctypes.byref(c), hp)
+    return _load().oracle_step_n(_dptr(U), nx, ny, ctypes.byref(c), int(step_index), hp)
 
 
 def totals(U: np.ndarray) -> np.ndarray:

@@ -54,6 +54,21 @@ double oracle_minmod(double a, double b) {
   return fmax(a, b);
 }
 
+/* Other limiters of van Leer's family, for the same one-sided differences:
+ *   MC (monotonized central): sign(a) min(2|a|, 2|b|, |a+b|/2),
+ *   van Leer: the harmonic mean 2ab/(a+b);
+ * both 0 unless a and b have the same sign. */
+double oracle_limit(double a, double b, int limiter) {
+  if (limiter == ORACLE_LIMITER_MINMOD) return oracle_minmod(a, b);
+  if (a * b <= 0.0) return 0.0;
+  if (limiter == ORACLE_LIMITER_MC) {
+    double m = fmin(2.0 * fabs(a), 2.0 * fabs(b));
+    m = fmin(m, 0.5 * fabs(a + b));
+    return a > 0.0 ? m : -m;
+  }
+  return 2.0 * a * b / (a + b);
+}
+
 /* MUSCL-Hancock half-step trace (reading; no characteristic projection).
  * The primitive 1D Euler system q_t + A(q) q_x = 0 advanced by half a step
  * with the limited slope as q_x gives the source S = -A(q) dq:
@@ -251,8 +266,8 @@ void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
   for (int j = 1; j < m - 1; j++) {
     double dq[4];
     for (int k = 0; k < 4; k++)
-      dq[k] = oracle_minmod(q[4 * j + k] - q[4 * (j - 1) + k],
-                            q[4 * (j + 1) + k] - q[4 * j + k]);
+      dq[k] = oracle_limit(q[4 * j + k] - q[4 * (j - 1) + k],
+                           q[4 * (j + 1) + k] - q[4 * j + k], c->limiter);
     oracle_trace(&q[4 * j], dq, g, lam, &qm[4 * j], &qp[4 * j]);
   }
   /* Riemann problem and flux at interfaces -1/2 .. n-1/2: interface between
@@ -371,12 +386,18 @@ double oracle_compute_dt(const double *U, int nx, int ny, const oracle_cfg *c) {
   return c->cfl * h / oracle_max_speed(U, nx, ny, c->gamma);
 }
 
+double oracle_step_n(double *U, int nx, int ny, const oracle_cfg *c,
+                     long step_index, long long *hist) {
+  double dt = oracle_compute_dt(U, nx, ny, c);
+  const int yx = c->order == ORACLE_ORDER_ALTERNATE && (step_index & 1);
+  oracle_sweep(U, nx, ny, yx ? ORACLE_DIR_Y : ORACLE_DIR_X, dt, c, hist);
+  oracle_sweep(U, nx, ny, yx ? ORACLE_DIR_X : ORACLE_DIR_Y, dt, c, hist);
+  return dt;
+}
+
 double oracle_step(double *U, int nx, int ny, const oracle_cfg *c,
                    long long *hist) {
-  double dt = oracle_compute_dt(U, nx, ny, c);
-  oracle_sweep(U, nx, ny, ORACLE_DIR_X, dt, c, hist);
-  oracle_sweep(U, nx, ny, ORACLE_DIR_Y, dt, c, hist);
-  return dt;
+  return oracle_step_n(U, nx, ny, c, 0, hist);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -23,7 +23,9 @@
  * (minmod-limited slopes, MUSCL-Hancock half-step trace in primitive
  * variables, two-shock Riemann solver iterated by Newton from the
  * two-rarefaction guess, linear fan sampling, CFL time step).  Every reading
- * is listed next to the function that takes it.
+ * is listed next to the function that takes it.  Options beyond them: the
+ * MC and van Leer limiters, and sweep orders that alternate x-y / y-x
+ * between steps (Strang-type symmetrisation of the splitting).
  *
  * Layout: a grid is double U[4][ny][nx] (x fastest), variables
  * (rho, rho*u, rho*v, E).  Pencils are rows (x-sweep) or columns (y-sweep).
@@ -48,12 +50,21 @@ extern "C" {
 #define ORACLE_RHO_MIN 1e-10
 #define ORACLE_C_MIN 1e-10
 
+#define ORACLE_LIMITER_MINMOD 0
+#define ORACLE_LIMITER_MC 1       /* monotonized central */
+#define ORACLE_LIMITER_VANLEER 2
+
+#define ORACLE_ORDER_XY 0         /* x-sweep then y-sweep every step */
+#define ORACLE_ORDER_ALTERNATE 1  /* x then y on even steps, y then x on odd */
+
 typedef struct {
   double gamma; /* ratio of specific heats, > 1 */
   double cfl;   /* Courant number, (0, 1] */
   int bc;       /* ORACLE_BC_* */
   int niter;    /* Newton iteration cap (10) */
   double tol;   /* convergence test |dp| <= tol * p (1e-8) */
+  int limiter;  /* ORACLE_LIMITER_* (minmod) */
+  int order;    /* ORACLE_ORDER_* (x then y) */
 } oracle_cfg;
 
 /* conservative (rho, m_n, m_t, E) -> primitive (rho, u_n, u_t, p), floored */
@@ -65,6 +76,8 @@ double oracle_sound_speed(const double q[4], double gamma);
 
 /* limited slope of one variable from its two one-sided differences */
 double oracle_minmod(double a, double b);
+/* the same for any ORACLE_LIMITER_* */
+double oracle_limit(double a, double b, int limiter);
 
 /* MUSCL-Hancock half-step trace of one cell: primitive state q, limited
  * slopes dq, lambda = dt/h.  qm is the state at the cell's left face
@@ -116,9 +129,12 @@ double oracle_max_speed(const double *U, int nx, int ny, double gamma);
 /* dt = cfl * h / max speed */
 double oracle_compute_dt(const double *U, int nx, int ny, const oracle_cfg *c);
 
-/* one time step: dt from U, x-sweep, y-sweep.  Returns dt. */
+/* one time step: dt from U, then the two sweeps (x then y, or with
+ * ORACLE_ORDER_ALTERNATE y then x when step_index is odd).  Returns dt. */
 double oracle_step(double *U, int nx, int ny, const oracle_cfg *c,
                    long long *hist);
+double oracle_step_n(double *U, int nx, int ny, const oracle_cfg *c,
+                     long step_index, long long *hist);
 
 /* sum over interior cells of each conserved variable times h^2 */
 void oracle_totals(const double *U, int nx, int ny, double out[4]);

@@ -353,3 +353,101 @@ def test_threads_do_not_change_results(orc):
     orc.step(b, c, hist)
     assert np.array_equal(a, b)
     assert hist.sum() == 2 * 40 * 36 + 36 + 40  # interfaces of both sweeps
+
+
+# ---------------------------------------------------------------- limiters, sweep order
+@pytest.mark.parametrize("lim", [0, 1, 2])
+def test_limiter_properties(orc, lim):
+    """Every limiter: 0 for opposite signs or a zero difference, symmetric,
+    odd, phi(a, a) = a, and between minmod and twice minmod."""
+    rng = np.random.Generator(np.random.PCG64(90 + lim))
+    for a, b in rng.normal(size=(400, 2)) * np.exp(rng.uniform(-5, 5, (400, 1))):
+        v = orc.limit(a, b, lim)
+        assert orc.limit(b, a, lim) == pytest.approx(v, rel=1e-15, abs=0)
+        assert orc.limit(-a, -b, lim) == -v
+        if a * b <= 0:
+            assert v == 0.0
+        else:
+            m = min(abs(a), abs(b))
+            assert np.sign(v) == np.sign(a)
+            assert m * (1 - 1e-15) <= abs(v) <= 2 * m * (1 + 1e-15)
+        assert orc.limit(a, a, lim) == pytest.approx(a, rel=1e-15)
+    assert orc.limit(0.0, 1.0, lim) == 0.0
+
+
+def test_limiter_values(orc):
+    """Hand-evaluated cases: minmod takes the smaller difference, MC the
+    smallest of twice each and the central mean, van Leer the harmonic mean."""
+    assert orc.limit(1.0, 3.0, 0) == 1.0
+    assert orc.limit(1.0, 3.0, 1) == 2.0        # min(2, 6, 2)
+    assert orc.limit(1.0, 2.0, 1) == 1.5        # min(2, 4, 1.5)
+    assert orc.limit(-1.0, -9.0, 1) == -2.0     # min(2, 18, 5)
+    assert orc.limit(1.0, 3.0, 2) == 1.5        # 2*3/4
+    assert orc.limit(2.0, 6.0, 2) == 3.0        # 2*12/8
+    assert orc.limit(-4.0, -4.0, 2) == -4.0
+
+
+@pytest.mark.parametrize("lim", [1, 2])
+def test_other_limiters_second_order(orc, lim):
+    """A smooth entropy wave converges at second order with MC and van Leer."""
+    errs = []
+    for n in (64, 128):
+        x = (np.arange(n) + 0.5) / n
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        U = inputs.conservative(rho[None, :].repeat(2, 0), np.ones((2, n)), np.zeros((2, n)),
+                                np.ones((2, n)))
+        c = orc.cfg(bc=3, cfl=0.4, limiter=lim)
+        t = 0.0
+        while t < 0.25 - 1e-14:
+            dt = orc.compute_dt(U, c)
+            dt = min(dt, 0.25 - t)
+            orc.sweep(U, 0, dt, c)
+            t += dt
+        exact = 1.0 + 0.2 * np.sin(2 * np.pi * (x - 0.25))
+        errs.append(np.abs(U[0, 0] - exact).mean())
+    assert np.log2(errs[0] / errs[1]) > 1.6
+
+
+def test_sharper_limiters_resolve_contact_better(orc):
+    """Sod's tube at t ~ 0.2: the compressive limiters (MC, van Leer) leave a
+    smaller L1 density error against the exact cell averages than minmod."""
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    n = 200
+    err = {}
+    for lim in (0, 1, 2):
+        U = inputs.shock_tube(n, 2, (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1))
+        c = orc.cfg(bc=orc.BC_OUTFLOW, limiter=lim)
+        t, _ = run_until(orc, U, c, 0.2)
+        ref = ex.cell_averages(L, R, np.arange(n + 1) / n, t)
+        err[lim] = np.abs(U[0, 0, :] - ref[0]).sum() / n
+    assert err[1] < err[0] and err[2] < err[0], err
+
+
+def test_alternating_order(orc):
+    """Alternating sweep order: even steps x then y, odd steps y then x; data
+    uniform in y is unaffected by the order (its y-sweeps change nothing);
+    totals are conserved under periodic boundaries."""
+    U = inputs.random_states(24, 17, seed=5, rough=0.6)
+    c0, c1 = orc.cfg(bc=3), orc.cfg(bc=3, order=1)
+    a, b = U.copy(), U.copy()
+    dt = orc.step(b, c1, step_index=1)
+    orc.sweep(a, 1, dt, c0)
+    orc.sweep(a, 0, dt, c0)
+    np.testing.assert_array_equal(a, b)
+    a, b = U.copy(), U.copy()
+    orc.step(a, c0, step_index=0)
+    orc.step(b, c1, step_index=0)
+    np.testing.assert_array_equal(a, b)
+    T0 = orc.totals(U)
+    V = U.copy()
+    for s in range(6):
+        orc.step(V, c1, step_index=s)
+    np.testing.assert_allclose(orc.totals(V), T0, rtol=1e-13, atol=1e-13)
+    row = inputs.random_states(40, 1, seed=6, rough=0.6)
+    W = np.repeat(row, 5, axis=1)
+    W[2] = 0.0  # no transverse velocity
+    p, q = W.copy(), W.copy()
+    for s in range(3):
+        orc.step(p, c0, step_index=s)
+        orc.step(q, c1, step_index=s)
+    np.testing.assert_allclose(q, p, rtol=0, atol=1e-14 * np.abs(p).max())
