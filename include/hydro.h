@@ -69,9 +69,18 @@ enum {
 
 #define HYDRO_LEARNED_GATE_DEFAULT 1.0
 
+/* Slope limiters (options.limiter): minmod (default); MC, the monotonized
+ * central sign(a) min(2|a|, 2|b|, |a+b|/2); van Leer's harmonic mean
+ * 2ab/(a+b); all 0 unless both one-sided differences a, b share a sign. */
+enum { HYDRO_LIMITER_MINMOD = 0, HYDRO_LIMITER_MC = 1, HYDRO_LIMITER_VANLEER = 2 };
+/* Sweep order (options.order): x then y every step (default), or x then y
+ * on even steps and y then x on odd steps (by the handle's step count). */
+enum { HYDRO_ORDER_XY = 0, HYDRO_ORDER_ALTERNATE = 1 };
+
 /* Solver options (hydro_set_options).  Defaults: niter 10, tol 1e-8,
  * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library,
- * learned_gate HYDRO_LEARNED_GATE_DEFAULT. */
+ * learned_gate HYDRO_LEARNED_GATE_DEFAULT, limiter HYDRO_LIMITER_MINMOD,
+ * order HYDRO_ORDER_XY. */
 typedef struct {
   int niter;     /* Newton iteration cap, 1..HYDRO_MAX_NITER              */
   double tol;    /* convergence test |dp| <= tol * p, > 0                  */
@@ -87,6 +96,8 @@ typedef struct {
                     is above when max(pL,pR) > e^s min(pL,pR) or
                     (uR-uL)^2 (rhoL+rhoR) > s^2 gamma (pL+pR).  s <= 0: every
                     interface takes the learned guess.  Finite, <= 50.     */
+  int limiter;   /* HYDRO_LIMITER_*                                        */
+  int order;     /* HYDRO_ORDER_*                                          */
 } hydro_options_t;
 
 /* Riemann-solver statistics accumulated since the last reset

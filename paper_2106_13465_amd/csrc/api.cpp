@@ -106,6 +106,10 @@ int check_options(const hydro::Plan* p, const hydro_options_t* o) {
   if (o->seg_y < 0 || o->seg_y > (1 << 20)) return fail(HYDRO_EINVAL, "seg_y %d", o->seg_y);
   if (!std::isfinite(o->learned_gate) || o->learned_gate > 50.0)
     return fail(HYDRO_EINVAL, "learned_gate %g: must be finite and <= 50", o->learned_gate);
+  if (o->limiter < HYDRO_LIMITER_MINMOD || o->limiter > HYDRO_LIMITER_VANLEER)
+    return fail(HYDRO_EINVAL, "limiter %d", o->limiter);
+  if (o->order != HYDRO_ORDER_XY && o->order != HYDRO_ORDER_ALTERNATE)
+    return fail(HYDRO_EINVAL, "order %d", o->order);
   return HYDRO_OK;
 }
 
@@ -405,6 +409,7 @@ int hydro_set_clock(hydro_t* h, double t, long step) {
   DeviceGuard g(h->device);
   hipError_t e = hydro::launch_set_clock(h->st, 0, t, step, h->stream);
   if (e != hipSuccess) return dev_fail(e, "hydro_set_clock");
+  h->host_step = step;
   return HYDRO_OK;
 }
 

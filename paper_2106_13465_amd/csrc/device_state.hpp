@@ -54,6 +54,8 @@ struct Extras {
   float gamma;
   float gate_kappa;                // learned guess where pmax > kappa pmin (0: everywhere)
   float gate_theta2;               // ... or du^2 (rL+rR) > theta2 gamma (pL+pR)
+  int fuse;                        // 1: fold the max wave speed of the sweep's
+                                   // output into st[].acc (last sweep of a step)
 };
 constexpr int kLogFields = 8;
 

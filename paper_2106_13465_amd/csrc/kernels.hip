@@ -18,8 +18,9 @@
 // y-sweep (columns): one thread per column marches down a segment of rows
 //   with a register window of the 5-cell stencil (paper, Figure 2); lanes
 //   run along x, so every load and store of the wave is one coalesced row
-//   access without an LDS transpose.  The epilogue computes the max wave
-//   speed of the new state for the grid's next dt (fused CFL reduction).
+//   access without an LDS transpose.
+// The last sweep of a step computes the max wave speed of the new state in
+// its epilogue, for the grid's next dt (fused CFL reduction).
 //
 // Both read the grid's stored dt from device memory, so a step launches
 // without a host round trip and can be captured into a HIP graph.
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
     T* outp = b.dst + d.off + (long long)row * d.pitch;
     const long long P = d.plane;
     int status = 0;
+    T smax = T(0);  // max wave speed of the written cells (ex.fuse)
 
     for (int sgi = 0; sgi < b.seg; ++sgi) {
       const int seg = seg0 + sgi;
@@ -213,10 +215,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
       const Prim<T> ql = from_left(q);
       const Prim<T> qr = from_right(q);
       Prim<T> dq;
-      dq.r = minmod(q.r - ql.r, qr.r - q.r);
-      dq.u = minmod(q.u - ql.u, qr.u - q.u);
-      dq.t = minmod(q.t - ql.t, qr.t - q.t);
-      dq.p = minmod(q.p - ql.p, qr.p - q.p);
+      dq.r = limit(q.r - ql.r, qr.r - q.r, G.limiter);
+      dq.u = limit(q.u - ql.u, qr.u - q.u, G.limiter);
+      dq.t = limit(q.t - ql.t, qr.t - q.t, G.limiter);
+      dq.p = limit(q.p - ql.p, qr.p - q.p, G.limiter);
       Prim<T> qm, qp;
       trace(q, ir, dq, lam, G, qm, qp);
 
@@ -254,9 +256,14 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
         outp[2 * P + i] = nt;
         outp[3 * P + i] = ne;
         status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+        if (ex.fuse) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
       }
     }
     if (status) atomicOr(&st->status, status);
+    if (ex.fuse) {  // wave-uniform
+      const double wmax = wave_max((double)smax);
+      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
+    }
   }
 }
 
@@ -267,12 +274,13 @@ struct Cell {
 };
 
 template <typename T>
-__device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c) {
+__device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c,
+                                          int limiter) {
   Prim<T> d;
-  d.r = minmod(b.r - a.r, c.r - b.r);
-  d.u = minmod(b.u - a.u, c.u - b.u);
-  d.t = minmod(b.t - a.t, c.t - b.t);
-  d.p = minmod(b.p - a.p, c.p - b.p);
+  d.r = limit(b.r - a.r, c.r - b.r, limiter);
+  d.u = limit(b.u - a.u, c.u - b.u, limiter);
+  d.t = limit(b.t - a.t, c.t - b.t, limiter);
+  d.p = limit(b.p - a.p, c.p - b.p, limiter);
   return d;
 }
 
@@ -329,7 +337,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
       ir1 = ir2;
       c2 = load(j + 2);
       q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
-      if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2), lam, G, qm1, qp1);
+      if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2, G.limiter), lam, G, qm1, qp1);
       if (j >= y0 - 1) {
         T p_learned = T(0);
         if (GUESS)
@@ -362,15 +370,17 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
           __builtin_nontemporal_store(nn, out + 2 * P + off);
           __builtin_nontemporal_store(ne, out + 3 * P + off);
           status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-          smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+          if (ex.fuse) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
         }
       }
       qp0 = qp1;
       Fm = F;
     }
     if (status) atomicOr(&st->status, status);
-    const double wmax = wave_max((double)smax);
-    if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
+    if (ex.fuse) {  // wave-uniform
+      const double wmax = wave_max((double)smax);
+      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
+    }
   }
 }
 

@@ -10,8 +10,8 @@
 namespace hydro {
 
 // instr: Newton statistics and (if ex.log) the interface logger; guess: 1 =
-// learned starting guess from ex.mlp.  The y-sweep always fuses the max wave
-// speed of its output into st[].acc.
+// learned starting guess from ex.mlp.  With ex.fuse the sweep folds the max
+// wave speed of its output into st[].acc (the last sweep of a step).
 template <typename T>
 hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s);

@@ -39,6 +39,7 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   // the guess use repeated squaring instead of exp2/log2
   const double k = std::nearbyint(1.0 / z);
   G.ipow_k = (k >= 1.0 && k <= 64.0 && std::fabs(1.0 / z - k) <= 1e-12 * k) ? (int)k : 0;
+  G.limiter = o.limiter;
   return G;
 }
 
@@ -249,9 +250,9 @@ hipError_t Plan::enqueue_finalize(bool advance, bool reset) {
   return launch_finalize_dt(d_desc, st, n, advance, reset, stream);
 }
 
-hipError_t Plan::enqueue_sweep(int dir, const void* src, void* dst) {
-  // (the y-sweep always fuses the max wave speed of its output)
+hipError_t Plan::enqueue_sweep(int dir, bool fuse, const void* src, void* dst) {
   Extras ex;
+  ex.fuse = fuse ? 1 : 0;
   ex.mlp = mlp;
   ex.log = log;
   ex.log_count = log_count;
@@ -309,20 +310,26 @@ hipError_t Plan::enqueue_step() {
     PhaseTimer pt(this, HYDRO_PHASE_DT);
     HIP_TRY(enqueue_finalize(true, true));
   }
+  // x then y, or y then x on odd steps with the alternating order; the
+  // second sweep folds the max wave speed of the new state into st[].acc
+  const bool yx = opt.order == HYDRO_ORDER_ALTERNATE && (host_step & 1);
+  const int first = yx ? HYDRO_DIR_Y : HYDRO_DIR_X;
+  const int second = yx ? HYDRO_DIR_X : HYDRO_DIR_Y;
   {
-    PhaseTimer pt(this, HYDRO_PHASE_SWEEP_X);
-    HIP_TRY(enqueue_sweep(HYDRO_DIR_X, U, V));
+    PhaseTimer pt(this, first == HYDRO_DIR_X ? HYDRO_PHASE_SWEEP_X : HYDRO_PHASE_SWEEP_Y);
+    HIP_TRY(enqueue_sweep(first, false, U, V));
   }
   {
-    PhaseTimer pt(this, HYDRO_PHASE_SWEEP_Y);
-    HIP_TRY(enqueue_sweep(HYDRO_DIR_Y, V, U));
+    PhaseTimer pt(this, second == HYDRO_DIR_X ? HYDRO_PHASE_SWEEP_X : HYDRO_PHASE_SWEEP_Y);
+    HIP_TRY(enqueue_sweep(second, true, V, U));
   }
+  ++host_step;
   acc_valid = true;
   return hipSuccess;
 }
 
 hipError_t Plan::enqueue_single_sweep(int dir) {
-  HIP_TRY(enqueue_sweep(dir, U, V));
+  HIP_TRY(enqueue_sweep(dir, false, U, V));
   acc_valid = false;
   if (dtype == HYDRO_F64) return launch_copy<double>(batch_of<double>(*this, V, U, 0, rows), stream);
   return launch_copy<float>(batch_of<float>(*this, V, U, 0, rows), stream);
@@ -342,12 +349,17 @@ hipError_t Plan::graph_launch(int nsteps) {
     HIP_TRY(enqueue_max_speed());
     acc_valid = true;
   }
-  if (!gexec || graph_steps != nsteps) {
+  // the captured sweep orders depend on the starting step's parity when the
+  // order alternates
+  const int parity = opt.order == HYDRO_ORDER_ALTERNATE ? (int)(host_step & 1) : 0;
+  const long long start = host_step;
+  if (!gexec || graph_steps != nsteps || graph_parity != parity) {
     drop_graph();
     const bool prof = profiling;
     profiling = false;
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = enqueue_step();
+    host_step = start;
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(stream, &graph);
     profiling = prof;
@@ -359,8 +371,11 @@ hipError_t Plan::graph_launch(int nsteps) {
       return e;
     }
     graph_steps = nsteps;
+    graph_parity = parity;
   }
-  return hipGraphLaunch(gexec, stream);
+  HIP_TRY(hipGraphLaunch(gexec, stream));
+  host_step = start + nsteps;
+  return hipSuccess;
 }
 
 hipError_t Plan::sync_states(std::vector<DevState>& out) {
@@ -415,10 +430,10 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     auto time_it = [&](int dir, const LaunchCfg& c, int reps, double& ms) -> hipError_t {
       cfg = c;
       HIP_TRY(upload_descriptors());
-      HIP_TRY(enqueue_sweep(dir, U, V));
+      HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
       HIP_TRY(hipEventRecord(ev[0], stream));
       for (int r = 0; r < reps; ++r) {
-        HIP_TRY(enqueue_sweep(dir, U, V));
+        HIP_TRY(enqueue_sweep(dir, dir == HYDRO_DIR_Y, U, V));
         HIP_TRY(hipEventRecord(ev[r + 1], stream));
       }
       HIP_TRY(hipEventSynchronize(ev[reps]));

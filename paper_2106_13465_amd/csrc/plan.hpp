@@ -61,6 +61,8 @@ struct Plan {
   // captured multi-step graph
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0;
+  int graph_parity = 0;       // starting step parity the graph was captured for
+  long long host_step = 0;    // steps enqueued (mirrors the device step count)
   // learned guess (borrowed device network) and interface logger
   const MlpDev* mlp = nullptr;
   float* log = nullptr;
@@ -85,8 +87,8 @@ struct Plan {
 
   hipError_t enqueue_max_speed();          // st[].acc <- max speed of U
   hipError_t enqueue_finalize(bool advance, bool reset);
-  hipError_t enqueue_sweep(int dir, const void* src, void* dst);
-  hipError_t enqueue_step();               // dt (fused max), x-sweep U->V, y-sweep V->U
+  hipError_t enqueue_sweep(int dir, bool fuse, const void* src, void* dst);
+  hipError_t enqueue_step();  // dt (fused max), first sweep U->V, second V->U (fused max)
   hipError_t enqueue_single_sweep(int dir);  // U->V, copy back
   hipError_t enqueue_totals();
   hipError_t graph_launch(int nsteps);

@@ -1,0 +1,124 @@
+"""Options beyond the default method: the MC and van Leer limiters and the
+alternating sweep order, each against the FP64 oracle with the same option,
+including graph replay (whose captured sweep order depends on the starting
+step's parity) and the batched path."""
+import numpy as np
+import pytest
+
+from paper_2106_13465_amd import inputs
+from test_gpu_parity import TOL64, make, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("bc", [1, 3])
+@pytest.mark.parametrize("limiter", [1, 2])
+def test_limiters_fp64(torch_cuda, orc, limiter, bc):
+    U = inputs.random_states(130, 75, seed=60 + limiter, rough=0.6)
+    h = make(torch_cuda, U, bc, limiter=limiter)
+    h.step(5)
+    ref = U.copy()
+    c = orc.cfg(bc=bc, limiter=limiter)
+    for _ in range(5):
+        orc.step(ref, c)
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("limiter", [0, 1, 2])
+def test_limiters_fp32_l1(torch_cuda, orc, limiter):
+    U = inputs.random_smooth(160, 120, seed=70, amp=0.5)
+    h = make(torch_cuda, U, 3, dtype=torch_cuda.float32, limiter=limiter)
+    h.step(10)
+    ref = U.copy()
+    c = orc.cfg(bc=3, limiter=limiter)
+    for _ in range(10):
+        orc.step(ref, c)
+    got = h.get_state().astype(np.float64)
+    for k in range(4):
+        assert np.abs(got[k] - ref[k]).sum() / np.abs(ref[k]).sum() < 1e-5
+
+
+@pytest.mark.parametrize("bc", [1, 2, 3])
+def test_alternating_order_fp64(torch_cuda, orc, bc):
+    U = inputs.random_states(110, 90, seed=80 + bc, rough=0.6)
+    h = make(torch_cuda, U, bc, order=1)
+    h.step(6)
+    t, step, _ = h.clock()
+    ref = U.copy()
+    c = orc.cfg(bc=bc, order=1)
+    t_or = sum(orc.step(ref, c, step_index=s) for s in range(6))
+    assert step == 6 and abs(t - t_or) <= 1e-13 * t_or
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
+def test_alternating_order_graph_parity(torch_cuda, orc):
+    """Graph replays of 3 steps start on alternating parities (the graph is
+    recaptured for each); the result equals 6 eager steps bitwise and the
+    oracle's 6 steps with the same order."""
+    U = inputs.random_states(96, 70, seed=91, rough=0.6)
+    a = make(torch_cuda, U, 3, order=1)
+    b = make(torch_cuda, U, 3, order=1)
+    a.step(6)
+    b.graph_steps(3)
+    b.graph_steps(3)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    ref = U.copy()
+    c = orc.cfg(bc=3, order=1)
+    for s in range(6):
+        orc.step(ref, c, step_index=s)
+    assert rel_err(b.get_state(), ref) <= TOL64
+
+
+def test_alternating_order_restart(torch_cuda, orc):
+    """A restart at an odd step count resumes with the y-first order."""
+    U = inputs.random_states(64, 48, seed=92, rough=0.6)
+    a = make(torch_cuda, U, 2, order=1)
+    a.step(3)
+    mid = a.get_state()
+    t, step, _ = a.clock()
+    a.step(2)
+    b = make(torch_cuda, mid, 2, order=1)
+    b.set_clock(t, step)
+    b.step(2)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+
+
+def test_batch_options(torch_cuda, orc):
+    from paper_2106_13465_amd.hydro import HydroBatch
+
+    shapes = [(70, 33), (45, 91), (128, 64)]
+    bcs = [1, 3, 2]
+    states = [inputs.random_states(nx, ny, seed=200 + g, rough=0.6)
+              for g, (nx, ny) in enumerate(shapes)]
+    b = HydroBatch(shapes, 1.4, 0.8, bcs, dtype=torch_cuda.float64)
+    b.set_options(limiter=2, order=1)
+    b.set_states(states)
+    b.graph_steps(2)
+    b.step(3)
+    got = b.get_states()
+    for g, U in enumerate(states):
+        ref = U.copy()
+        c = orc.cfg(bc=bcs[g], limiter=2, order=1)
+        for s in range(5):
+            orc.step(ref, c, step_index=s)
+        assert rel_err(got[g], ref) <= TOL64, g
+
+
+def test_option_validation(torch_cuda):
+    from paper_2106_13465_amd.hydro import Hydro, HydroError
+
+    h = Hydro(16, 16, 1.4, 0.8, "periodic")
+    with pytest.raises(HydroError):
+        h.set_options(limiter=3)
+    with pytest.raises(HydroError):
+        h.set_options(order=2)
+    o = h.options()
+    assert o["limiter"] == 0 and o["order"] == 0
