@@ -34,7 +34,7 @@ struct Gas {
   int niter;   // Newton iteration cap
   int niter_learned;  // cap from a learned guess before falling back
   int ipow_k;  // 1/z when it is a small integer (7 for gamma = 1.4), else 0
-  int limiter; // HYDRO_LIMITER_*: 0 minmod, 1 MC, 2 van Leer
+  int limiter; // HYDRO_LIMITER_*: 0 minmod, 1 MC, 2 van Leer (selects the kernel)
 };
 
 template <typename T>
@@ -63,16 +63,22 @@ __device__ __forceinline__ T minmod(T a, T b) {
   return a * b > T(0) ? copysign(fmin(fabs(a), fabs(b)), a) : T(0);
 }
 
-// Limited slope from the two one-sided differences (limiter uniform across
-// the wave): minmod; MC, sign(a) min(2|a|, 2|b|, |a+b|/2); van Leer,
-// 2ab/(a+b); 0 unless a and b share a sign.
-template <typename T>
-__device__ __forceinline__ T limit(T a, T b, int limiter) {
-  if (limiter == 0) return minmod(a, b);
-  if (!(a * b > T(0))) return T(0);
-  if (limiter == 1)
-    return copysign(fmin(fmin(T(2) * fabs(a), T(2) * fabs(b)), T(0.5) * fabs(a + b)), a);
-  return T(2) * a * b * fm::rcp(a + b);
+// Limited slope from the two one-sided differences: LIM 0 minmod, 1 MC,
+// sign(a) min(2|a|, 2|b|, |a+b|/2), 2 van Leer, 2ab/(a+b); 0 unless a and b
+// share a sign.  A template argument, so the tile code of each limiter is
+// straight-line (a runtime switch splits it into basic blocks the scheduler
+// cannot interleave across).
+template <int LIM, typename T>
+__device__ __forceinline__ T limit(T a, T b) {
+  if constexpr (LIM == 0) {
+    return minmod(a, b);
+  } else {
+    if (!(a * b > T(0))) return T(0);
+    if constexpr (LIM == 1)
+      return copysign(fmin(fmin(T(2) * fabs(a), T(2) * fabs(b)), T(0.5) * fabs(a + b)), a);
+    else
+      return T(2) * a * b * fm::rcp(a + b);
+  }
 }
 
 // MUSCL-Hancock half-step trace of one cell: face states at x_{i-1/2} (qm)

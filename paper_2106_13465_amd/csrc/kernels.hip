@@ -26,6 +26,8 @@
 // without a host round trip and can be captured into a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "device_state.hpp"
 #include "godunov.hpp"
 #include "launch.hpp"
@@ -177,7 +179,7 @@ struct SweepOcc {
   static constexpr int y = kOcc[4 + v];
 };
 
-template <typename T, bool INSTR, int GUESS>
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
     T* outp = b.dst + d.off + (long long)row * d.pitch;
     const long long P = d.plane;
     int status = 0;
-    T smax = T(0);  // max wave speed of the written cells (ex.fuse)
+    T smax = T(0);  // max wave speed of the written cells (FUSE)
 
     for (int sgi = 0; sgi < b.seg; ++sgi) {
       const int seg = seg0 + sgi;
@@ -215,10 +217,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
       const Prim<T> ql = from_left(q);
       const Prim<T> qr = from_right(q);
       Prim<T> dq;
-      dq.r = limit(q.r - ql.r, qr.r - q.r, G.limiter);
-      dq.u = limit(q.u - ql.u, qr.u - q.u, G.limiter);
-      dq.t = limit(q.t - ql.t, qr.t - q.t, G.limiter);
-      dq.p = limit(q.p - ql.p, qr.p - q.p, G.limiter);
+      dq.r = limit<LIM>(q.r - ql.r, qr.r - q.r);
+      dq.u = limit<LIM>(q.u - ql.u, qr.u - q.u);
+      dq.t = limit<LIM>(q.t - ql.t, qr.t - q.t);
+      dq.p = limit<LIM>(q.p - ql.p, qr.p - q.p);
       Prim<T> qm, qp;
       trace(q, ir, dq, lam, G, qm, qp);
 
@@ -256,11 +258,11 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
         outp[2 * P + i] = nt;
         outp[3 * P + i] = ne;
         status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-        if (ex.fuse) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+        if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
       }
     }
     if (status) atomicOr(&st->status, status);
-    if (ex.fuse) {  // wave-uniform
+    if constexpr (FUSE) {
       const double wmax = wave_max((double)smax);
       if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
     }
@@ -273,18 +275,17 @@ struct Cell {
   T r, n, t, e;  // conservative: density, normal (y) and transverse (x) momentum, energy
 };
 
-template <typename T>
-__device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c,
-                                          int limiter) {
+template <int LIM, typename T>
+__device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, const Prim<T>& c) {
   Prim<T> d;
-  d.r = limit(b.r - a.r, c.r - b.r, limiter);
-  d.u = limit(b.u - a.u, c.u - b.u, limiter);
-  d.t = limit(b.t - a.t, c.t - b.t, limiter);
-  d.p = limit(b.p - a.p, c.p - b.p, limiter);
+  d.r = limit<LIM>(b.r - a.r, c.r - b.r);
+  d.u = limit<LIM>(b.u - a.u, c.u - b.u);
+  d.t = limit<LIM>(b.t - a.t, c.t - b.t);
+  d.p = limit<LIM>(b.p - a.p, c.p - b.p);
   return d;
 }
 
-template <typename T, bool INSTR, int GUESS>
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
       ir1 = ir2;
       c2 = load(j + 2);
       q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
-      if (j >= y0 - 2) trace(q1, ir1, slopes(q0, q1, q2, G.limiter), lam, G, qm1, qp1);
+      if (j >= y0 - 2) trace(q1, ir1, slopes<LIM>(q0, q1, q2), lam, G, qm1, qp1);
       if (j >= y0 - 1) {
         T p_learned = T(0);
         if (GUESS)
@@ -370,14 +371,14 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
           __builtin_nontemporal_store(nn, out + 2 * P + off);
           __builtin_nontemporal_store(ne, out + 3 * P + off);
           status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-          if (ex.fuse) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+          if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
         }
       }
       qp0 = qp1;
       Fm = F;
     }
     if (status) atomicOr(&st->status, status);
-    if (ex.fuse) {  // wave-uniform
+    if constexpr (FUSE) {
       const double wmax = wave_max((double)smax);
       if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
     }
@@ -526,53 +527,62 @@ static inline unsigned blocks_for(long long items, unsigned max_blocks) {
   return (unsigned)(nb > 0 ? nb : 1);
 }
 
+// Sweep kernel variants: instrumentation, learned guess, fused reduction and
+// limiter are template arguments; index = instr + 2 guess + 4 fuse + 8 limiter.
+template <typename T>
+using SweepFn = void (*)(Batch<T>, Gas<T>, Extras);
+constexpr int kSweepVariants = 2 * 2 * 2 * 3;
+
+template <typename T, int DIR, int V>
+constexpr SweepFn<T> sweep_variant() {
+  constexpr bool I = V & 1;
+  constexpr int GS = (V >> 1) & 1;
+  constexpr bool F = (V >> 2) & 1;
+  constexpr int L = V >> 3;
+  if constexpr (DIR == 0)
+    return &k_sweep_x<T, I, GS, L, F>;
+  else
+    return &k_sweep_y<T, I, GS, L, F>;
+}
+
+template <typename T, int DIR, int... V>
+SweepFn<T> sweep_table(int v, std::integer_sequence<int, V...>) {
+  static const SweepFn<T> table[] = {sweep_variant<T, DIR, V>()...};
+  return table[v];
+}
+
+template <typename T, int DIR>
+SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter) {
+  const int v = (instr ? 1 : 0) + (guess ? 2 : 0) + (fuse ? 4 : 0) + 8 * limiter;
+  return sweep_table<T, DIR>(v, std::make_integer_sequence<int, kSweepVariants>());
+}
+
 template <typename T>
 hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
-  if (guess) {
-    if (instr)
-      hipLaunchKernelGGL((k_sweep_x<T, true, 1>), grid, block, 0, s, b, G, ex);
-    else
-      hipLaunchKernelGGL((k_sweep_x<T, false, 1>), grid, block, 0, s, b, G, ex);
-  } else {
-    if (instr)
-      hipLaunchKernelGGL((k_sweep_x<T, true, 0>), grid, block, 0, s, b, G, ex);
-    else
-      hipLaunchKernelGGL((k_sweep_x<T, false, 0>), grid, block, 0, s, b, G, ex);
-  }
+  if (G.limiter < 0 || G.limiter > 2) return hipErrorInvalidValue;
+  const SweepFn<T> k = sweep_kernel<T, 0>(instr, guess, ex.fuse != 0, G.limiter);
+  hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
+                     s, b, G, ex);
   return hipGetLastError();
 }
 
 template <typename T>
-int sweep_y_blocks_per_cu(bool instr, int guess) {
+int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter) {
+  if (limiter < 0 || limiter > 2) return 0;
   int nb = 0;
-  const int threads = kWave * kWavesPerBlock;
-  hipError_t e;
-  if (guess)
-    e = instr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, true, 1>, threads, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, false, 1>, threads, 0);
-  else
-    e = instr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, true, 0>, threads, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_y<T, false, 0>, threads, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, sweep_kernel<T, 1>(instr, guess, fuse, limiter), kWave * kWavesPerBlock, 0);
   return e == hipSuccess ? nb : 0;
 }
 
 template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  const dim3 grid(blocks_for(b.items, max_blocks)), block(kWave * kWavesPerBlock);
-  if (guess) {
-    if (instr)
-      hipLaunchKernelGGL((k_sweep_y<T, true, 1>), grid, block, 0, s, b, G, ex);
-    else
-      hipLaunchKernelGGL((k_sweep_y<T, false, 1>), grid, block, 0, s, b, G, ex);
-  } else {
-    if (instr)
-      hipLaunchKernelGGL((k_sweep_y<T, true, 0>), grid, block, 0, s, b, G, ex);
-    else
-      hipLaunchKernelGGL((k_sweep_y<T, false, 0>), grid, block, 0, s, b, G, ex);
-  }
+  if (G.limiter < 0 || G.limiter > 2) return hipErrorInvalidValue;
+  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, ex.fuse != 0, G.limiter);
+  hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
+                     s, b, G, ex);
   return hipGetLastError();
 }
 
@@ -625,7 +635,7 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
                                         int, unsigned, hipStream_t);                          \
   template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
                                         int, unsigned, hipStream_t);                          \
-  template int sweep_y_blocks_per_cu<T>(bool, int);                                           \
+  template int sweep_y_blocks_per_cu<T>(bool, int, bool, int);                                \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
   template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);

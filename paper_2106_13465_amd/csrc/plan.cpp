@@ -480,8 +480,9 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     {
       const bool instr = opt.stats != 0 || log != nullptr;
       const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
-      const int bpc = dtype == HYDRO_F64 ? sweep_y_blocks_per_cu<double>(instr, guess)
-                                         : sweep_y_blocks_per_cu<float>(instr, guess);
+      const int bpc = dtype == HYDRO_F64
+                          ? sweep_y_blocks_per_cu<double>(instr, guess, true, opt.limiter)
+                          : sweep_y_blocks_per_cu<float>(instr, guess, true, opt.limiter);
       const long long slots = (long long)cus * bpc * kWavesPerBlock;
       auto items_for = [&](int sy) {
         long long it = 0;
