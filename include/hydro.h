@@ -192,8 +192,8 @@ int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
  * items fill whole rounds of the resident waves) times persistent block
  * counts; the three fastest are re-timed and the lowest median wins.  U is
  * not modified; the fused max speed is invalidated.  use_cache reuses the
- * result of an earlier tuning of the same grid shapes and dtype in this
- * process.  Synchronises.  out may be NULL. */
+ * result of an earlier tuning of the same grid shapes, dtype, starting guess
+ * and limiter in this process.  Synchronises.  out may be NULL. */
 int hydro_autotune(hydro_t *h, hydro_tune_t *out, int use_cache);
 
 /* Kernel timing.  While enabled, hydro_step records a HIP event pair on the

@@ -66,6 +66,19 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Fold a non-negative wave maximum into a grid's max-speed accumulator (bits
+// of a double >= 0 order as unsigned integers).  Atomics on one address
+// serialise in L2, so the atomic is skipped when the value read already
+// covers v: the accumulator only grows within a step, so a stale read costs
+// at most a redundant atomic.  Without the check a launch with one small work
+// item per wave (the x-sweep: ~1.5e5 items on 8192^2) spends milliseconds on
+// them.  Called by one lane.
+__device__ __forceinline__ void fold_max(unsigned long long* acc, double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  if (bits > __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(acc, bits);
+}
+
 __device__ __forceinline__ void count_newton(DevState* st, bool valid, int key) {
   const int lane = threadIdx.x & (kWave - 1);
   bool mine = valid;
@@ -264,7 +277,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
     if (status) atomicOr(&st->status, status);
     if constexpr (FUSE) {
       const double wmax = wave_max((double)smax);
-      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
+      if (lane == 0) fold_max(&st->acc, wmax);
     }
   }
 }
@@ -380,7 +393,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
     if (status) atomicOr(&st->status, status);
     if constexpr (FUSE) {
       const double wmax = wave_max((double)smax);
-      if (lane == 0) atomicMax(&st->acc, (unsigned long long)__double_as_longlong(wmax));
+      if (lane == 0) fold_max(&st->acc, wmax);
     }
   }
 }
@@ -399,7 +412,7 @@ __global__ __launch_bounds__(256) void k_max_speed(Batch<T> b, Gas<T> G) {
     for (int x = lane; x < d.nx; x += kWave)
       smax = fmax(smax, (double)max_speed(rp[x], rp[P + x], rp[2 * P + x], rp[3 * P + x], G));
     smax = wave_max(smax);
-    if (lane == 0) atomicMax(&b.st[gi].acc, (unsigned long long)__double_as_longlong(smax));
+    if (lane == 0) fold_max(&b.st[gi].acc, smax);
   }
 }
 

@@ -388,9 +388,11 @@ hipError_t Plan::sync_states(std::vector<DevState>& out) {
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, std::vector<int>>, LaunchCfg> g_tune_cache;
+// keyed by dtype, kernel variant (starting guess, limiter) and grid shapes
+using TuneKey = std::tuple<int, int, int, std::vector<int>>;
+std::map<TuneKey, LaunchCfg> g_tune_cache;
 
-std::tuple<int, std::vector<int>> tune_key(const Plan& p) {
+TuneKey tune_key(const Plan& p) {
   std::vector<int> shape;
   shape.reserve(3 * p.n);
   for (int g = 0; g < p.n; ++g) {
@@ -398,7 +400,8 @@ std::tuple<int, std::vector<int>> tune_key(const Plan& p) {
     shape.push_back(p.ny[g]);
     shape.push_back(p.bc[g]);
   }
-  return {p.dtype, shape};
+  const int guess = (p.opt.guess == HYDRO_GUESS_MLP && p.mlp) ? 1 : 0;
+  return {p.dtype, guess, p.opt.limiter, shape};
 }
 
 }  // namespace
