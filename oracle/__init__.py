@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 BC_REFLECT, BC_OUTFLOW, BC_PERIODIC = 1, 2, 3
 LIMITER_MINMOD, LIMITER_MC, LIMITER_VANLEER = 0, 1, 2
 ORDER_XY, ORDER_ALTERNATE = 0, 1
+RIEMANN_TWO_SHOCK, RIEMANN_EXACT, RIEMANN_HLLC = 0, 1, 2
 DIR_X, DIR_Y = 0, 1
 RHO_MIN = 1e-10
 C_MIN = 1e-10
@@ -38,6 +39,7 @@ class Cfg(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("limiter", ctypes.c_int),
         ("order", ctypes.c_int),
+        ("riemann", ctypes.c_int),
     ]
 
 
@@ -69,6 +71,13 @@ def _load():
             [_D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D, _D,
              ctypes.POINTER(ctypes.c_int)],
         ),
+        "oracle_exact_f": (ctypes.c_double, [_D, _D, ctypes.c_double, ctypes.c_double]),
+        "oracle_riemann_exact": (
+            ctypes.c_int,
+            [_D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D, _D,
+             ctypes.POINTER(ctypes.c_int)]),
+        "oracle_hllc_speeds": (None, [_D, _D, ctypes.c_double, _D]),
+        "oracle_hllc_flux": (None, [_D, _D, ctypes.c_double, _D]),
         "oracle_flux": (None, [_D, ctypes.c_double, _D]),
         "oracle_pencil": (None, [_D, ctypes.c_int, ctypes.c_double, ctypes.POINTER(Cfg), _LL]),
         "oracle_load_pencil": (
@@ -114,9 +123,9 @@ def _vec(x) -> np.ndarray:
 
 
 def cfg(gamma=1.4, cfl=0.8, bc=BC_PERIODIC, niter=10, tol=1e-8, limiter=LIMITER_MINMOD,
-        order=ORDER_XY) -> Cfg:
+        order=ORDER_XY, riemann=RIEMANN_TWO_SHOCK) -> Cfg:
     return Cfg(float(gamma), float(cfl), int(bc), int(niter), float(tol), int(limiter),
-               int(order))
+               int(order), int(riemann))
 
 
 # ---------------------------------------------------------------- single steps
@@ -170,6 +179,37 @@ def riemann(qL, qR, gamma=1.4, niter=10, tol=1e-8):
     it = _load().oracle_riemann(_dptr(qL), _dptr(qR), gamma, niter, tol, _dptr(qg),
                                 ctypes.byref(ps), ctypes.byref(us), ctypes.byref(conv))
     return qg, ps.value, us.value, it, bool(conv.value)
+
+
+def exact_f(qL, qR, gamma, p) -> float:
+    qL, qR = _vec(qL), _vec(qR)
+    return _load().oracle_exact_f(_dptr(qL), _dptr(qR), gamma, float(p))
+
+
+def riemann_exact(qL, qR, gamma=1.4, niter=10, tol=1e-8):
+    """Exact solver; returns (godunov_state[4], pstar, ustar, iterations, converged)."""
+    qL, qR = _vec(qL), _vec(qR)
+    qg = np.zeros(4)
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    conv = ctypes.c_int()
+    it = _load().oracle_riemann_exact(_dptr(qL), _dptr(qR), gamma, niter, tol, _dptr(qg),
+                                      ctypes.byref(ps), ctypes.byref(us), ctypes.byref(conv))
+    return qg, ps.value, us.value, it, bool(conv.value)
+
+
+def hllc_speeds(qL, qR, gamma=1.4) -> np.ndarray:
+    """(S_L, S*, S_R) of the HLLC flux."""
+    qL, qR = _vec(qL), _vec(qR)
+    S = np.zeros(3)
+    _load().oracle_hllc_speeds(_dptr(qL), _dptr(qR), gamma, S.ctypes.data_as(_D))
+    return S
+
+
+def hllc_flux(qL, qR, gamma=1.4) -> np.ndarray:
+    qL, qR = _vec(qL), _vec(qR)
+    F = np.zeros(4)
+    _load().oracle_hllc_flux(_dptr(qL), _dptr(qR), gamma, _dptr(F))
+    return F
 
 
 def flux(qg, gamma=1.4) -> np.ndarray:

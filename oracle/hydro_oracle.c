@@ -246,6 +246,201 @@ void oracle_flux(const double qg[4], double gamma, double F[4]) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Other interface solvers (options).  The paper names its Riemann solver     */
+/* only by reference [4]; besides the two-shock reading above, the exact      */
+/* solver of the Euler Riemann problem and the HLLC approximate flux.         */
+/* ------------------------------------------------------------------------ */
+
+/* Exact wave curve of side K and its derivative at pressure p:
+ *   shock (p > p_K):       f_K = (p - p_K) sqrt(A_K / (p + B_K)),
+ *                          A_K = 2 / ((gamma+1) rho_K),
+ *                          B_K = (gamma-1)/(gamma+1) p_K,
+ *                          f_K' = sqrt(A_K / (p + B_K)) (1 - (p - p_K) / (2 (p + B_K)))
+ *   rarefaction (p <= p_K): f_K = 2 c_K/(gamma-1) ((p/p_K)^z - 1),
+ *                          z = (gamma-1)/(2 gamma),
+ *                          f_K' = (p/p_K)^(-(gamma+1)/(2 gamma)) / (rho_K c_K) */
+static void exact_curve(const double q[4], double gamma, double p, double *f,
+                        double *df) {
+  double rho = q[0], pK = q[3];
+  if (p > pK) {
+    double A = 2.0 / ((gamma + 1.0) * rho);
+    double B = (gamma - 1.0) / (gamma + 1.0) * pK;
+    double s = sqrt(A / (p + B));
+    *f = (p - pK) * s;
+    *df = s * (1.0 - (p - pK) / (2.0 * (p + B)));
+  } else {
+    double c = oracle_sound_speed(q, gamma);
+    double z = (gamma - 1.0) / (2.0 * gamma);
+    *f = 2.0 * c / (gamma - 1.0) * (pow(p / pK, z) - 1.0);
+    *df = pow(p / pK, -(gamma + 1.0) / (2.0 * gamma)) / (rho * c);
+  }
+}
+
+double oracle_exact_f(const double qL[4], const double qR[4], double gamma,
+                      double p) {
+  double fL, dfL, fR, dfR;
+  exact_curve(qL, gamma, p, &fL, &dfL);
+  exact_curve(qR, gamma, p, &fR, &dfR);
+  return fL + fR + (qR[1] - qL[1]);
+}
+
+int oracle_riemann_exact(const double qL[4], const double qR[4], double gamma,
+                         int niter, double tol, double qg[4], double *pstar_out,
+                         double *ustar_out, int *converged) {
+  const double g = gamma;
+  double pmin = pmin_of(qL, qR, g);
+
+  /* star pressure: Newton on the exact f from the two-rarefaction guess,
+   * with the same floor and stopping test as the two-shock solver */
+  double p = oracle_ptr_guess(qL, qR, g);
+  int k = 0, conv = 0;
+  while (k < niter) {
+    k++;
+    double fL, dfL, fR, dfR;
+    exact_curve(qL, g, p, &fL, &dfL);
+    exact_curve(qR, g, p, &fR, &dfR);
+    double dp = -(fL + fR + (qR[1] - qL[1])) / (dfL + dfR);
+    p = fmax(p + dp, pmin);
+    if (fabs(dp) <= tol * p) {
+      conv = 1;
+      break;
+    }
+  }
+
+  /* star velocity u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2 */
+  double fL, dfL, fR, dfR;
+  exact_curve(qL, g, p, &fL, &dfL);
+  exact_curve(qR, g, p, &fR, &dfR);
+  double us = 0.5 * (qL[1] + qR[1]) + 0.5 * (fR - fL);
+
+  /* the self-similar solution at x/t = 0; u* = 0 goes to the left side (the
+   * tie reading of the two-shock solver) */
+  double G6 = (g - 1.0) / (g + 1.0);
+  double z = (g - 1.0) / (2.0 * g);
+  double r, u, pr;
+  const double *qo;
+  if (us >= 0.0) { /* left of the contact */
+    qo = qL;
+    double rho = qL[0], uK = qL[1], pK = qL[3];
+    double c = oracle_sound_speed(qL, g);
+    if (p > pK) { /* left shock, speed u_L - c_L sqrt(...) */
+      double S = uK - c * sqrt((g + 1.0) / (2.0 * g) * p / pK + z);
+      if (S >= 0.0) {
+        r = rho, u = uK, pr = pK;
+      } else {
+        r = rho * (p / pK + G6) / (G6 * p / pK + 1.0), u = us, pr = p;
+      }
+    } else { /* left rarefaction: head u_L - c_L, tail u* - c*_L */
+      double head = uK - c;
+      double tail = us - c * pow(p / pK, z);
+      if (head >= 0.0) {
+        r = rho, u = uK, pr = pK;
+      } else if (tail < 0.0) {
+        r = rho * pow(p / pK, 1.0 / g), u = us, pr = p;
+      } else { /* inside the fan */
+        double cf = 2.0 / (g + 1.0) * (c + 0.5 * (g - 1.0) * uK);
+        r = rho * pow(cf / c, 2.0 / (g - 1.0));
+        u = cf;
+        pr = pK * pow(cf / c, 2.0 * g / (g - 1.0));
+      }
+    }
+  } else { /* right of the contact */
+    qo = qR;
+    double rho = qR[0], uK = qR[1], pK = qR[3];
+    double c = oracle_sound_speed(qR, g);
+    if (p > pK) { /* right shock, speed u_R + c_R sqrt(...) */
+      double S = uK + c * sqrt((g + 1.0) / (2.0 * g) * p / pK + z);
+      if (S <= 0.0) {
+        r = rho, u = uK, pr = pK;
+      } else {
+        r = rho * (p / pK + G6) / (G6 * p / pK + 1.0), u = us, pr = p;
+      }
+    } else { /* right rarefaction: head u_R + c_R, tail u* + c*_R */
+      double head = uK + c;
+      double tail = us + c * pow(p / pK, z);
+      if (head <= 0.0) {
+        r = rho, u = uK, pr = pK;
+      } else if (tail > 0.0) {
+        r = rho * pow(p / pK, 1.0 / g), u = us, pr = p;
+      } else { /* inside the fan */
+        double cf = 2.0 / (g + 1.0) * (c - 0.5 * (g - 1.0) * uK);
+        r = rho * pow(cf / c, 2.0 / (g - 1.0));
+        u = -cf;
+        pr = pK * pow(cf / c, 2.0 * g / (g - 1.0));
+      }
+    }
+  }
+  qg[0] = fmax(r, ORACLE_RHO_MIN);
+  qg[1] = u;
+  qg[2] = qo[2]; /* transverse velocity is carried by the contact */
+  qg[3] = pr;
+
+  if (pstar_out) *pstar_out = p;
+  if (ustar_out) *ustar_out = us;
+  if (converged) *converged = conv;
+  return k;
+}
+
+/* Wave-speed bounds of the HLLC flux: Einfeldt's, from the Roe averages
+ *   w = sqrt(rho),  a~ = (w_L a_L + w_R a_R)/(w_L + w_R) for a = u, v, H,
+ *   H = (E + p)/rho,  c~^2 = (gamma-1)(H~ - (u~^2 + v~^2)/2)  (floored at
+ *   c_min^2, a reading),
+ *   S_L = min(u_L - c_L, u~ - c~),  S_R = max(u_R + c_R, u~ + c~),
+ * and the contact speed
+ *   S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)) /
+ *        (rho_L (S_L - u_L) - rho_R (S_R - u_R)). */
+void oracle_hllc_speeds(const double qL[4], const double qR[4], double gamma,
+                        double S[3]) {
+  double g = gamma;
+  double cL = oracle_sound_speed(qL, g), cR = oracle_sound_speed(qR, g);
+  double HL = (g / (g - 1.0) * qL[3] + 0.5 * qL[0] * (qL[1] * qL[1] + qL[2] * qL[2])) / qL[0];
+  double HR = (g / (g - 1.0) * qR[3] + 0.5 * qR[0] * (qR[1] * qR[1] + qR[2] * qR[2])) / qR[0];
+  double wL = sqrt(qL[0]), wR = sqrt(qR[0]);
+  double ua = (wL * qL[1] + wR * qR[1]) / (wL + wR);
+  double va = (wL * qL[2] + wR * qR[2]) / (wL + wR);
+  double Ha = (wL * HL + wR * HR) / (wL + wR);
+  double c2 = (g - 1.0) * (Ha - 0.5 * (ua * ua + va * va));
+  double ca = sqrt(fmax(c2, ORACLE_C_MIN * ORACLE_C_MIN));
+  double SL = fmin(qL[1] - cL, ua - ca);
+  double SR = fmax(qR[1] + cR, ua + ca);
+  double mL = qL[0] * (SL - qL[1]), mR = qR[0] * (SR - qR[1]);
+  S[0] = SL;
+  S[1] = (qR[3] - qL[3] + qL[1] * mL - qR[1] * mR) / (mL - mR);
+  S[2] = SR;
+}
+
+/* HLLC flux (Toro, Spruce and Speares): with the speeds above and the star
+ * states
+ *   U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S*, v_K,
+ *          E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K)))),
+ * the flux at x/t = 0 is F_L if 0 <= S_L, F_L + S_L (U*_L - U_L) if
+ * S_L < 0 <= S*, F_R + S_R (U*_R - U_R) if S* < 0 < S_R, F_R if S_R <= 0
+ * (S* = 0 takes the left star state, the tie reading of the other solvers). */
+void oracle_hllc_flux(const double qL[4], const double qR[4], double gamma,
+                      double F[4]) {
+  double S[3];
+  oracle_hllc_speeds(qL, qR, gamma, S);
+  double SL = S[0], Ss = S[1], SR = S[2];
+  if (SL >= 0.0) {
+    oracle_flux(qL, gamma, F);
+    return;
+  }
+  if (SR <= 0.0) {
+    oracle_flux(qR, gamma, F);
+    return;
+  }
+  const double *q = Ss >= 0.0 ? qL : qR;
+  double SK = Ss >= 0.0 ? SL : SR;
+  double rho = q[0], u = q[1], v = q[2], p = q[3];
+  double E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+  double U[4] = {rho, rho * u, rho * v, E};
+  double a = rho * (SK - u) / (SK - Ss);
+  double Us[4] = {a, a * Ss, a * v, a * (E / rho + (Ss - u) * (Ss + p / (rho * (SK - u))))};
+  oracle_flux(q, gamma, F);
+  for (int k = 0; k < 4; k++) F[k] = F[k] + SK * (Us[k] - U[k]);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One pencil (Figure 5: READ into a 1D buffer, COMPUTE, WRITE back).          */
 /* ------------------------------------------------------------------------ */
 void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
@@ -273,10 +468,17 @@ void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
   /* Riemann problem and flux at interfaces -1/2 .. n-1/2: interface between
    * pencil columns j and j+1 is stored at F[j] */
   for (int j = 1; j < m - 2; j++) {
+    if (c->riemann == ORACLE_RIEMANN_HLLC) { /* no iteration to count */
+      oracle_hllc_flux(&qp[4 * j], &qm[4 * (j + 1)], g, &F[4 * j]);
+      continue;
+    }
     double qg[4];
     int conv;
-    int it = oracle_riemann(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter, c->tol,
-                            qg, NULL, NULL, &conv);
+    int it = c->riemann == ORACLE_RIEMANN_EXACT
+                 ? oracle_riemann_exact(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter,
+                                        c->tol, qg, NULL, NULL, &conv)
+                 : oracle_riemann(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter, c->tol,
+                                  qg, NULL, NULL, &conv);
     if (hist) hist[conv ? it : 0]++;
     oracle_flux(qg, g, &F[4 * j]);
   }

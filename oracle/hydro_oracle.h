@@ -25,7 +25,8 @@
  * two-rarefaction guess, linear fan sampling, CFL time step).  Every reading
  * is listed next to the function that takes it.  Options beyond them: the
  * MC and van Leer limiters, and sweep orders that alternate x-y / y-x
- * between steps (Strang-type symmetrisation of the splitting).
+ * between steps (Strang-type symmetrisation of the splitting), and two other
+ * interface solvers: the exact Riemann solver and the HLLC flux.
  *
  * Layout: a grid is double U[4][ny][nx] (x fastest), variables
  * (rho, rho*u, rho*v, E).  Pencils are rows (x-sweep) or columns (y-sweep).
@@ -54,6 +55,10 @@ extern "C" {
 #define ORACLE_LIMITER_MC 1       /* monotonized central */
 #define ORACLE_LIMITER_VANLEER 2
 
+#define ORACLE_RIEMANN_TWO_SHOCK 0 /* Newton on the two-shock function */
+#define ORACLE_RIEMANN_EXACT 1     /* Newton on the exact wave curves */
+#define ORACLE_RIEMANN_HLLC 2      /* HLLC flux, Einfeldt wave speeds */
+
 #define ORACLE_ORDER_XY 0         /* x-sweep then y-sweep every step */
 #define ORACLE_ORDER_ALTERNATE 1  /* x then y on even steps, y then x on odd */
 
@@ -65,6 +70,7 @@ typedef struct {
   double tol;   /* convergence test |dp| <= tol * p (1e-8) */
   int limiter;  /* ORACLE_LIMITER_* (minmod) */
   int order;    /* ORACLE_ORDER_* (x then y) */
+  int riemann;  /* ORACLE_RIEMANN_* (two-shock) */
 } oracle_cfg;
 
 /* conservative (rho, m_n, m_t, E) -> primitive (rho, u_n, u_t, p), floored */
@@ -103,6 +109,27 @@ int oracle_riemann(const double qL[4], const double qR[4], double gamma,
                    int niter, double tol, double qg[4], double *pstar,
                    double *ustar, int *converged);
 
+/* exact wave function f(p) = f_L(p) + f_R(p) + (u_R - u_L) with the shock
+ * and rarefaction curves of each side (its root is the exact p*) */
+double oracle_exact_f(const double qL[4], const double qR[4], double gamma,
+                      double p);
+
+/* Riemann problem solved exactly: Newton on the exact wave function from the
+ * two-rarefaction guess (same cap, test and floor as oracle_riemann), then
+ * the exact self-similar solution at x/t = 0, rarefaction fans included.
+ * Same arguments and return value as oracle_riemann. */
+int oracle_riemann_exact(const double qL[4], const double qR[4], double gamma,
+                         int niter, double tol, double qg[4], double *pstar,
+                         double *ustar, int *converged);
+
+/* HLLC wave speeds S = (S_L, S*, S_R) (Einfeldt's bounds, contact speed) */
+void oracle_hllc_speeds(const double qL[4], const double qR[4], double gamma,
+                        double S[3]);
+
+/* HLLC flux through the interface between primitive states qL and qR */
+void oracle_hllc_flux(const double qL[4], const double qR[4], double gamma,
+                      double F[4]);
+
 /* Euler flux normal to the interface from the Godunov state */
 void oracle_flux(const double qg[4], double gamma, double F[4]);
 
@@ -110,7 +137,8 @@ void oracle_flux(const double qg[4], double gamma, double F[4]);
  * the pencil at column i+2 (ghosts at 0,1 and n+2,n+3), variables
  * (rho, m_n, m_t, E).  Cells 0..n-1 are updated in place with
  * lambda = dt/h.  hist (may be NULL) has niter+1 slots: hist[k] counts
- * interfaces converged after k iterations, hist[0] the unconverged ones. */
+ * interfaces converged after k iterations, hist[0] the unconverged ones (the
+ * HLLC flux iterates nothing and counts nothing). */
 void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
                    long long *hist);
 
