@@ -62,10 +62,11 @@ def workload(name: str, n: int):
 
 LIMITERS = {"minmod": 0, "mc": 1, "vanleer": 2}
 ORDERS = {"xy": 0, "alternate": 1}
+SOLVERS = {"two_shock": 0, "exact": 1, "hllc": 2}
 
 
 def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True, limiter=0,
-            order=0):
+            order=0, riemann=0):
     import torch
 
     from paper_2106_13465_amd.hydro import Hydro
@@ -73,7 +74,7 @@ def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True, l
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     _, ny, nx = U.shape
     h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0")
-    h.set_options(limiter=limiter, order=order)
+    h.set_options(limiter=limiter, order=order, riemann=riemann)
     if seg_x or seg_y:
         h.set_options(seg_x=seg_x, seg_y=seg_y)
     h.set_state(U)
@@ -138,12 +139,12 @@ def pmc_traffic(workload_name: str, kernel: str, dtype_name: str):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(U, bc_name, limiter=0, order=0):
+def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
     import oracle
 
     bc = {"periodic": oracle.BC_PERIODIC, "reflect": oracle.BC_REFLECT,
           "outflow": oracle.BC_OUTFLOW}[bc_name]
-    c = oracle.cfg(bc=bc, limiter=limiter, order=order)
+    c = oracle.cfg(bc=bc, limiter=limiter, order=order, riemann=riemann)
     V = U.copy()
     _, ny, nx = V.shape
     t0 = time.perf_counter()
@@ -533,6 +534,8 @@ def main() -> int:
                     help="slope limiter of the reconstruction")
     ap.add_argument("--order", choices=sorted(ORDERS), default="xy",
                     help="sweep order: x then y every step, or alternating xy / yx")
+    ap.add_argument("--riemann", choices=sorted(SOLVERS), default="two_shock",
+                    help="interface solver")
     ap.add_argument("--seg-x", type=int, default=0)
     ap.add_argument("--seg-y", type=int, default=0)
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -576,7 +579,8 @@ def main() -> int:
         print(f"# gpu {dn}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
               flush=True)
         h, r = run_gpu(U, bc, dn, args.steps, args.warmup, args.seg_x, args.seg_y,
-                       not args.no_autotune, LIMITERS[args.limiter], ORDERS[args.order])
+                       not args.no_autotune, LIMITERS[args.limiter], ORDERS[args.order],
+                       SOLVERS[args.riemann])
         elem = 8 if dn == "f64" else 4
         ms_step = r["ms_total"] / args.steps
         sx = sweep_record(cells, elem, r["profile"]["sweep_x"])
@@ -606,8 +610,8 @@ def main() -> int:
     res = results[main_dn]
     sx, sy = res["sweeps"]["x"], res["sweeps"]["y"]
     dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
-    # the counter summaries are taken with the default limiter and order
-    default_opts = args.limiter == "minmod" and args.order == "xy"
+    # the counter summaries are taken with the default limiter, order and solver
+    default_opts = args.limiter == "minmod" and args.order == "xy" and args.riemann == "two_shock"
     traffic = pmc_traffic(args.workload, dom_name, main_dn) if default_opts else None
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
@@ -629,6 +633,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": desc, "nx": nx, "ny": ny, "bc": bc, "gamma": 1.4, "cfl": 0.8,
                    "limiter": args.limiter, "sweep_order": args.order,
+                   "riemann": args.riemann,
                    "newton_cap": 10, "newton_tol": 1e-8,
                    "parallelism": "single GPU"},
         "sweeps": res["sweeps"],
@@ -647,7 +652,8 @@ def main() -> int:
     del states
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(U, bc, LIMITERS[args.limiter], ORDERS[args.order])
+        line["cpu_baseline"] = cpu_baseline(U, bc, LIMITERS[args.limiter], ORDERS[args.order],
+                                            SOLVERS[args.riemann])
     print(json.dumps(line), flush=True)
     return 0
 

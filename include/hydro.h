@@ -76,11 +76,21 @@ enum { HYDRO_LIMITER_MINMOD = 0, HYDRO_LIMITER_MC = 1, HYDRO_LIMITER_VANLEER = 2
 /* Sweep order (options.order): x then y every step (default), or x then y
  * on even steps and y then x on odd steps (by the handle's step count). */
 enum { HYDRO_ORDER_XY = 0, HYDRO_ORDER_ALTERNATE = 1 };
+/* Interface solver (options.riemann).  The paper delegates its Riemann
+ * solver to a reference (Section 1); the default reading is the two-shock
+ * solver, Newton from the two-rarefaction guess.  HYDRO_RIEMANN_EXACT: the
+ * exact Riemann solver, Newton on the exact shock and rarefaction curves from
+ * the same guess with the same cap, test and floors, then the exact
+ * self-similar state at x/t = 0 (rarefaction fans included).
+ * HYDRO_RIEMANN_HLLC: the HLLC flux with Einfeldt's wave bounds from Roe
+ * averages; no iteration, so Riemann statistics and the interface logger
+ * record nothing and the learned guess is rejected (HYDRO_EINVAL). */
+enum { HYDRO_RIEMANN_TWO_SHOCK = 0, HYDRO_RIEMANN_EXACT = 1, HYDRO_RIEMANN_HLLC = 2 };
 
 /* Solver options (hydro_set_options).  Defaults: niter 10, tol 1e-8,
  * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library,
  * learned_gate HYDRO_LEARNED_GATE_DEFAULT, limiter HYDRO_LIMITER_MINMOD,
- * order HYDRO_ORDER_XY. */
+ * order HYDRO_ORDER_XY, riemann HYDRO_RIEMANN_TWO_SHOCK. */
 typedef struct {
   int niter;     /* Newton iteration cap, 1..HYDRO_MAX_NITER              */
   double tol;    /* convergence test |dp| <= tol * p, > 0                  */
@@ -98,6 +108,7 @@ typedef struct {
                     interface takes the learned guess.  Finite, <= 50.     */
   int limiter;   /* HYDRO_LIMITER_*                                        */
   int order;     /* HYDRO_ORDER_*                                          */
+  int riemann;   /* HYDRO_RIEMANN_*                                        */
 } hydro_options_t;
 
 /* Riemann-solver statistics accumulated since the last reset
@@ -192,8 +203,8 @@ int hydro_riemann_stats(hydro_t *h, hydro_stats_t *s, int reset);
  * items fill whole rounds of the resident waves) times persistent block
  * counts; the three fastest are re-timed and the lowest median wins.  U is
  * not modified; the fused max speed is invalidated.  use_cache reuses the
- * result of an earlier tuning of the same grid shapes, dtype, starting guess
- * and limiter in this process.  Synchronises.  out may be NULL. */
+ * result of an earlier tuning of the same grid shapes, dtype, starting guess,
+ * limiter and solver in this process.  Synchronises.  out may be NULL. */
 int hydro_autotune(hydro_t *h, hydro_tune_t *out, int use_cache);
 
 /* Kernel timing.  While enabled, hydro_step records a HIP event pair on the

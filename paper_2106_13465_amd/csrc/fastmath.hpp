@@ -9,8 +9,9 @@
 //   rounding of the last operations (about one ulp) for the positive normal
 //   arguments the sweep passes (densities and pressures are floored far above
 //   the denormal range).  sqrt(x) = x * (1/sqrt(x)).  Fractional powers
-//   (two-rarefaction guess only) are range-reduced onto the FP32
-//   instructions; x^(-1/k) adds one FP64 Newton step.
+//   for starting guesses are range-reduced onto the FP32 instructions;
+//   x^(-1/k) adds one FP64 Newton step (two where the power enters the
+//   result: the exact solver's wave curves).
 // FP32: the single hardware instructions (about one ulp).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -90,6 +91,23 @@ __device__ __forceinline__ float root_inv(float x, int k, float inv_k) {
   (void)k;
   return exp2(-inv_k * log2(x));
 }
+
+// x^(-1/k) to full precision (the exact Riemann solver's wave curves, where
+// the power enters the result rather than a starting guess): a second Newton
+// step after root_inv takes the ~k 1e-14 error to rounding level.
+__device__ __forceinline__ double root_inv_full(double x, int k, double inv_k) {
+  const double y = root_inv(x, k, inv_k);
+  return fma(-y * inv_k, fma(x, ipow(y, k), -1.0), y);
+}
+__device__ __forceinline__ float root_inv_full(float x, int k, float inv_k) {
+  return root_inv(x, k, inv_k);
+}
+
+// x^a for positive normal x to full precision, any exponent: the device
+// library's pow in FP64 (only for ratios of specific heats whose exponents
+// are not integers), the FP32 instructions in FP32.
+__device__ __forceinline__ double pow_full(double x, double a) { return ::pow(x, a); }
+__device__ __forceinline__ float pow_full(float x, float a) { return pow_pos(x, a); }
 
 }  // namespace fm
 }  // namespace hydro

@@ -1,7 +1,8 @@
 // godunov.hpp -- device numerics of one 1D second-order Godunov update:
-// primitive variables, minmod slopes, MUSCL-Hancock trace, two-shock Riemann
-// solver and interface flux (paper, Section 1 and Figure 5; the numerical
-// readings are stated in include/hydro.h).  Written for gfx950, templated on
+// primitive variables, limited slopes, MUSCL-Hancock trace, the interface
+// solver (two-shock Riemann solver by default; the exact Riemann solver and
+// the HLLC flux as options) and interface flux (paper, Section 1 and
+// Figure 5; the numerical readings are stated in include/hydro.h).  Written for gfx950, templated on
 // the arithmetic type (double or float).  Divisions and square roots go
 // through the hardware-approximation layer of fastmath.hpp and are arranged
 // to share reciprocals: per Newton iteration two reciprocal square roots and
@@ -35,6 +36,12 @@ struct Gas {
   int niter_learned;  // cap from a learned guess before falling back
   int ipow_k;  // 1/z when it is a small integer (7 for gamma = 1.4), else 0
   int limiter; // HYDRO_LIMITER_*: 0 minmod, 1 MC, 2 van Leer (selects the kernel)
+  int riemann; // HYDRO_RIEMANN_*: 0 two-shock, 1 exact, 2 HLLC (selects the kernel)
+  T g6;        // (gamma - 1) / (gamma + 1)
+  T two_gp1;   // 2 / (gamma + 1)
+  T half_gp1;  // (gamma + 1) / 2
+  T rare_coef; // 2 / (gamma - 1)
+  int ipow_r;  // 2/(gamma - 1) when it is a small integer (5 for gamma = 1.4), else 0
 };
 
 template <typename T>
@@ -109,18 +116,105 @@ struct Flux {
   T m, n, t, e;
 };
 
+// Euler flux of a primitive state normal to the interface.
+template <typename T>
+__device__ __forceinline__ Flux<T> euler_flux(T r, T u, T t, T p, const Gas<T>& G) {
+  Flux<T> F;
+  F.m = r * u;
+  F.n = F.m * u + p;
+  F.t = F.m * t;
+  F.e = u * (G.h_coef * p + T(0.5) * r * (u * u + t * t));
+  return F;
+}
+
+// Exact wave curve of one side at pressure p and its derivative (ip = 1/p):
+//   shock (p > p_K): f = (p - p_K) s, s = sqrt(A/(p + B)) = 1/sqrt((gamma+1)/2
+//     rho_K (p + B)), B = (gamma-1)/(gamma+1) p_K, f' = s (1 - (p - p_K)/(2 (p + B)))
+//     with 1/(p + B) = s^2 (gamma+1)/2 rho_K;
+//   rarefaction: f = 2 c_K/(gamma-1) (y - 1), y = (p/p_K)^z,
+//     f' = (p/p_K)^(z-1)/(rho_K c_K) = y (p_K/p) iz_K, iz_K = 1/(rho_K c_K).
+template <typename T>
+__device__ __forceinline__ void exact_curve(T p, T ip, T rK, T pK, T cK, T izK, const Gas<T>& G,
+                                            T& f, T& df) {
+  if (p > pK) {
+    const T a = G.half_gp1 * rK;
+    const T s = fm::rsqrt(a * (p + G.g6 * pK));
+    f = (p - pK) * s;
+    df = s * (T(1) - T(0.5) * (p - pK) * (s * s) * a);
+  } else {
+    const T x = pK * ip;  // (p/p_K)^-1
+    const T y = G.ipow_k > 0 ? fm::root_inv_full(x, G.ipow_k, G.z) : fm::pow_full(x, -G.z);
+    f = G.rare_coef * cK * (y - T(1));
+    df = y * x * izK;
+  }
+}
+
+// HLLC flux (Toro, Spruce and Speares) between primitive states L and R with
+// Einfeldt's wave bounds from Roe averages (sqrt-density weights):
+//   S_L = min(u_L - c_L, u~ - c~), S_R = max(u_R + c_R, u~ + c~),
+//   c~^2 = (gamma-1)(H~ - (u~^2 + v~^2)/2) floored at c_min^2,
+//   S* = (p_R - p_L + u_L m_L - u_R m_R)/(m_L - m_R), m_K = rho_K (S_K - u_K);
+// flux F_L (0 <= S_L), F_R (S_R <= 0), else F_K + S_K (U*_K - U_K) on the
+// side K of the contact holding x/t = 0 (S* = 0 -> left), with
+//   U*_K = m_K/(S_K - S*) (1, S*, v_K, E_K/rho_K + (S* - u_K)(S* + p_K/m_K)).
+template <typename T>
+__device__ __forceinline__ Flux<T> hllc_flux(const Prim<T>& L, const Prim<T>& R,
+                                             const Gas<T>& G) {
+  const T qL = fm::rsqrt(L.r), qR = fm::rsqrt(R.r);  // 1/sqrt(rho)
+  const T irL = qL * qL, irR = qR * qR;
+  const T wL = L.r * qL, wR = R.r * qR;  // sqrt(rho)
+  const T cL = fm::sqrt(G.g * L.p * irL), cR = fm::sqrt(G.g * R.p * irR);
+  const T kL = T(0.5) * (L.u * L.u + L.t * L.t), kR = T(0.5) * (R.u * R.u + R.t * R.t);
+  const T HL = G.h_coef * L.p * irL + kL, HR = G.h_coef * R.p * irR + kR;
+  const T iw = fm::rcp(wL + wR);
+  const T ua = (wL * L.u + wR * R.u) * iw;
+  const T va = (wL * L.t + wR * R.t) * iw;
+  const T Ha = (wL * HL + wR * HR) * iw;
+  const T ca = fm::sqrt(fmax(G.gm1 * (Ha - T(0.5) * (ua * ua + va * va)), G.c_min * G.c_min));
+  const T SL = fmin(L.u - cL, ua - ca), SR = fmax(R.u + cR, ua + ca);
+  const T mL = L.r * (SL - L.u), mR = R.r * (SR - R.u);
+  const T Ss = (R.p - L.p + L.u * mL - R.u * mR) * fm::rcp(mL - mR);
+
+  const bool outL = SL >= T(0), outR = SR <= T(0);
+  const bool left = outL || (!outR && Ss >= T(0));
+  const T r = left ? L.r : R.r, u = left ? L.u : R.u, t = left ? L.t : R.t, p = left ? L.p : R.p;
+  Flux<T> F = euler_flux(r, u, t, p, G);
+  if (!outL && !outR) {
+    const T SK = left ? SL : SR, mK = left ? mL : mR;
+    const T irK = left ? irL : irR, kK = left ? kL : kR;
+    const T a = mK * fm::rcp(SK - Ss);
+    const T e_r = (G.h_coef - T(1)) * p * irK + kK;  // E / rho
+    F.m += SK * (a - r);
+    F.n += SK * (a * Ss - r * u);
+    F.t += SK * (a - r) * t;
+    F.e += SK * (a * (e_r + (Ss - u) * (Ss + p * fm::rcp(mK))) - r * e_r);
+  }
+  return F;
+}
+
 // Riemann problem at one interface: left state L, right state R.  Returns the
-// flux of the Godunov state at x/t = 0.  p_learned > 0 is a learned starting
+// flux of the Godunov state at x/t = 0.  RS: 0 the two-shock solver, 1 the
+// exact solver (Newton on the exact wave curves, exact sampling of the
+// self-similar solution, fans included), 2 the HLLC flux (no iteration:
+// iters = 0, converged, no learned guess).  p_learned > 0 is a learned starting
 // guess: Newton runs at most niter_learned iterations from it, and if the
 // convergence test has not been met the solve restarts from the
 // two-rarefaction guess with the full cap (fell_back).  p_learned < 0 means a
 // learned guess was produced but is unusable (also a fall-back); 0 means no
 // learned guess.  iters counts all iterations; pstar returns the final star
 // pressure.
-template <typename T>
+template <int RS, typename T>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
                                                 const Gas<T>& G, T p_learned, int& iters,
                                                 bool& converged, bool& fell_back, T& pstar) {
+  if constexpr (RS == 2) {
+    (void)p_learned;
+    iters = 0;
+    converged = true;
+    fell_back = false;
+    pstar = T(0);
+    return hllc_flux(L, R, G);
+  } else {
   T irL, irR, ipL, ipR;
   if constexpr (sizeof(T) == 8) {
     // FP64: the four reciprocals from one, 1/(rho_L rho_R p_L p_R) (the
@@ -164,18 +258,36 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   T p = learned ? fmax(p_learned, pmin) : two_rarefaction();
   int kmax = learned ? G.niter_learned : G.niter;
 
-  // Newton on f(p) = sum_K (p - p_K)/W_K + u_R - u_L with the two-shock
-  // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
-  // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
-  auto newton_step = [&](T& pp) -> bool {  // one iteration; true when converged
-    const T XL = CL * (T(1) + G.gs * (pp - L.p) * ipL);
-    const T XR = CR * (T(1) + G.gs * (pp - R.p) * ipR);
-    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
-    const T izL = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
-    const T izR = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
-    const T usL = L.u - (pp - L.p) * iWL;
-    const T usR = R.u + (pp - R.p) * iWR;
-    const T dp = (usL - usR) * fm::rcp(izL + izR);
+  // exact solver: 1/(rho_K c_K) = (1/rho_K) / c_K
+  T izL = T(0), izR = T(0);
+  if constexpr (RS == 1) {
+    izL = irL * fm::rcp(cL);
+    izR = irR * fm::rcp(cR);
+  }
+
+  // one Newton iteration on p; true when converged
+  auto newton_step = [&](T& pp) -> bool {
+    T dp;
+    if constexpr (RS == 0) {
+      // two-shock f(p) = sum_K (p - p_K)/W_K + u_R - u_L with
+      // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
+      // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
+      const T XL = CL * (T(1) + G.gs * (pp - L.p) * ipL);
+      const T XR = CR * (T(1) + G.gs * (pp - R.p) * ipR);
+      const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
+      const T izL2 = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
+      const T izR2 = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
+      const T usL = L.u - (pp - L.p) * iWL;
+      const T usR = R.u + (pp - R.p) * iWR;
+      dp = (usL - usR) * fm::rcp(izL2 + izR2);
+    } else {
+      // exact f(p) = f_L(p) + f_R(p) + u_R - u_L
+      const T ip = fm::rcp(pp);
+      T fL, dL, fR, dR;
+      exact_curve(pp, ip, L.r, L.p, cL, izL, G, fL, dL);
+      exact_curve(pp, ip, R.r, R.p, cR, izR, G, fR, dR);
+      dp = -(fL + fR + (R.u - L.u)) * fm::rcp(dL + dR);
+    }
     pp = fmax(pp + dp, pmin);
     return fabs(dp) <= G.tol * pp;
   };
@@ -204,61 +316,111 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   fell_back = fb || p_learned < T(0);
   pstar = p;
 
-  // star velocity (average of the two sides' estimates) at the final p
-  const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
-  const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
-  const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
-  const T usL = L.u - (p - L.p) * iWL;
-  const T usR = R.u + (p - R.p) * iWR;
-  const T us = T(0.5) * (usL + usR);
+  T gr, gu, gp, to;
+  if constexpr (RS == 0) {
+    // star velocity (average of the two sides' estimates) at the final p
+    const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
+    const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
+    const T usL = L.u - (p - L.p) * iWL;
+    const T usR = R.u + (p - R.p) * iWR;
+    const T us = T(0.5) * (usL + usR);
 
-  // upwind side of the contact (u* = 0 -> left)
-  const bool left = us >= T(0);
-  const T ro = left ? L.r : R.r;
-  const T uo = left ? L.u : R.u;
-  const T to = left ? L.t : R.t;
-  const T po = left ? L.p : R.p;
-  const T iro = left ? irL : irR;
-  const T co = left ? cL : cR;
-  const T Xo = left ? XL : XR;
-  const T iWo = left ? iWL : iWR;
+    // upwind side of the contact (u* = 0 -> left)
+    const bool left = us >= T(0);
+    const T ro = left ? L.r : R.r;
+    const T uo = left ? L.u : R.u;
+    to = left ? L.t : R.t;
+    const T po = left ? L.p : R.p;
+    const T iro = left ? irL : irR;
+    const T co = left ? cL : cR;
+    const T Xo = left ? XL : XR;
+    const T iWo = left ? iWL : iWR;
 
-  // star density: 1/rho* = 1/rho_o - (p* - p_o)/W_o^2, floored
-  T irs = iro + (po - p) * (iWo * iWo);
-  irs = fmin(irs, G.inv_rho_min);
-  const T rs = fm::rcp(irs);
-  const T cs = fmax(G.c_min, fm::sqrt(G.g * p * irs));
+    // star density: 1/rho* = 1/rho_o - (p* - p_o)/W_o^2, floored
+    T irs = iro + (po - p) * (iWo * iWo);
+    irs = fmin(irs, G.inv_rho_min);
+    const T rs = fm::rcp(irs);
+    const T cs = fmax(G.c_min, fm::sqrt(G.g * p * irs));
 
-  // outer/inner edge speeds of the wave on that side, positive away from the
-  // interface (s = +1 on the left, -1 on the right): a shock moves at
-  // W_o/rho_o - s u_o, a rarefaction spans c_o - s u_o .. c* - s u*
-  const T uos = left ? L.u : -R.u;  // s u_o
-  const T uss = left ? us : -us;    // s u*
-  const T wsh = Xo * iWo * iro - uos;
-  const bool shock = p >= po;
-  const T sout = shock ? wsh : co - uos;
-  const T sin_ = shock ? wsh : cs - uss;
+    // outer/inner edge speeds of the wave on that side, positive away from
+    // the interface (s = +1 on the left, -1 on the right): a shock moves at
+    // W_o/rho_o - s u_o, a rarefaction spans c_o - s u_o .. c* - s u*
+    const T uos = left ? L.u : -R.u;  // s u_o
+    const T uss = left ? us : -us;    // s u*
+    const T wsh = Xo * iWo * iro - uos;
+    const bool shock = p >= po;
+    const T sout = shock ? wsh : co - uos;
+    const T sin_ = shock ? wsh : cs - uss;
 
-  // x/t = 0 lies outside the wave (unperturbed side), inside the star
-  // region, or inside a rarefaction fan (linear across it)
-  const bool outside = sout < T(0);
-  T gr = outside ? ro : rs;
-  T gu = outside ? uo : us;
-  T gp = outside ? po : p;
-  if (!outside && !(sin_ > T(0))) {
-    T f = sout * fm::rcp(fmax(sout - sin_, G.c_min));
-    f = fmin(fmax(f, T(0)), T(1));
-    gr = f * rs + (T(1) - f) * ro;
-    gu = f * us + (T(1) - f) * uo;
-    gp = f * p + (T(1) - f) * po;
+    // x/t = 0 lies outside the wave (unperturbed side), inside the star
+    // region, or inside a rarefaction fan (linear across it)
+    const bool outside = sout < T(0);
+    gr = outside ? ro : rs;
+    gu = outside ? uo : us;
+    gp = outside ? po : p;
+    if (!outside && !(sin_ > T(0))) {
+      T f = sout * fm::rcp(fmax(sout - sin_, G.c_min));
+      f = fmin(fmax(f, T(0)), T(1));
+      gr = f * rs + (T(1) - f) * ro;
+      gu = f * us + (T(1) - f) * uo;
+      gp = f * p + (T(1) - f) * po;
+    }
+  } else {
+    // star velocity u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2
+    const T ip = fm::rcp(p);
+    T fL, dL, fR, dR;
+    exact_curve(p, ip, L.r, L.p, cL, izL, G, fL, dL);
+    exact_curve(p, ip, R.r, R.p, cR, izR, G, fR, dR);
+    const T us = T(0.5) * (L.u + R.u) + T(0.5) * (fR - fL);
+
+    // the exact solution at x/t = 0 on the side of the contact holding it
+    // (u* = 0 -> left), written for the left side with the right side
+    // mirrored (s u for each velocity u, s = -1 on the right)
+    const bool left = us >= T(0);
+    const T ro = left ? L.r : R.r;
+    const T uo = left ? L.u : R.u;
+    to = left ? L.t : R.t;
+    const T po = left ? L.p : R.p;
+    const T co = left ? cL : cR;
+    const T ratio = p * (left ? ipL : ipR);  // p*/p_o
+    const T uos = left ? uo : -uo;          // s u_o
+    const T uss = left ? us : -us;          // s u*
+    gr = ro;
+    gu = uo;
+    gp = po;
+    if (p > po) {  // shock at s u_o - c_o sqrt(gs p*/p_o + z)
+      const T S = uos - co * fm::sqrt(G.gs * ratio + G.z);
+      if (!(S >= T(0))) {
+        gr = ro * (ratio + G.g6) * fm::rcp(G.g6 * ratio + T(1));
+        gu = us;
+        gp = p;
+      }
+    } else {  // rarefaction: head s u_o - c_o, tail s u* - c_o (p*/p_o)^z
+      const T x = po * ip;  // (p*/p_o)^-1
+      const T y = G.ipow_k > 0 ? fm::root_inv_full(x, G.ipow_k, G.z) : fm::pow_full(x, -G.z);
+      const T head = uos - co;
+      const T tail = uss - co * y;
+      if (!(head >= T(0))) {
+        if (tail < T(0)) {  // star: rho_o (p*/p_o)^(1/gamma), 1/gamma = 1 - 2z
+          const T iy = fm::rcp(y);
+          gr = ro * ratio * (iy * iy);
+          gu = us;
+          gp = p;
+        } else {  // inside the fan
+          const T cf = G.two_gp1 * (co + G.half_gm1 * uos);
+          const T rc = cf * fm::rcp(co);
+          gr = ro * (G.ipow_r > 0 ? fm::ipow(rc, G.ipow_r) : fm::pow_full(rc, G.rare_coef));
+          gu = left ? cf : -cf;
+          gp = po * (G.ipow_k > 0 ? fm::ipow(rc, G.ipow_k) : fm::pow_full(rc, G.inv_z));
+        }
+      }
+    }
+    gr = fmax(gr, G.rho_min);
   }
 
-  Flux<T> F;
-  F.m = gr * gu;
-  F.n = F.m * gu + gp;
-  F.t = F.m * to;
-  F.e = gu * (G.h_coef * gp + T(0.5) * gr * (gu * gu + to * to));
-  return F;
+  return euler_flux(gr, gu, to, gp, G);
+  }
 }
 
 // Largest signal speed of a cell for the CFL condition: max(|u|+c, |v|+c).

@@ -185,15 +185,17 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 #define HYDRO_OCC 1, 1, 1, 6, 3, 1, 6, 5
 #endif
 constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 learned, then y
-template <typename T, int GUESS>
+// The exact solver's FP64 y-sweep needs more registers than 3 waves leave
+// (it spilled ~150 bytes per lane there); it asks for 2.
+template <typename T, int GUESS, int RS>
 struct SweepOcc {
   static constexpr int v = (sizeof(T) == 8 ? 0 : 2) + (GUESS ? 1 : 0);
   static constexpr int x = kOcc[v];
-  static constexpr int y = kOcc[4 + v];
+  static constexpr int y = (RS == 1 && sizeof(T) == 8 && kOcc[4 + v] > 2) ? 2 : kOcc[4 + v];
 };
 
-template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE>
-__global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS>
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::x)) void k_sweep_x(Batch<
       int iters;
       bool conv, fb;
       T pstar;
-      const Flux<T> F = riemann_flux(qp, qm_next, G, p_learned, iters, conv, fb, pstar);
+      const Flux<T> F = riemann_flux<RS>(qp, qm_next, G, p_learned, iters, conv, fb, pstar);
       const Flux<T> Fl = from_left(F);  // interface i-1/2
 
       if (INSTR) {
@@ -298,8 +300,8 @@ __device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, co
   return d;
 }
 
-template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE>
-__global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS>
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS>::y)) void k_sweep_y(Batch<
         int iters;
         bool conv, fb;
         T pstar;
-        F = riemann_flux(qp0, qm1, G, p_learned, iters, conv, fb, pstar);
+        F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar);
         if (INSTR) {
           const bool valid = xin && (j >= y0 || y0 == 0);
           count_newton(st, valid, conv ? iters : 0);
@@ -540,22 +542,27 @@ static inline unsigned blocks_for(long long items, unsigned max_blocks) {
   return (unsigned)(nb > 0 ? nb : 1);
 }
 
-// Sweep kernel variants: instrumentation, learned guess, fused reduction and
-// limiter are template arguments; index = instr + 2 guess + 4 fuse + 8 limiter.
+// Sweep kernel variants: instrumentation, learned guess, fused reduction,
+// limiter and interface solver are template arguments; index = instr +
+// 2 guess + 4 fuse + 8 limiter + 24 solver.  The HLLC flux iterates nothing,
+// so it has neither instrumented nor learned-guess variants (null entries).
 template <typename T>
 using SweepFn = void (*)(Batch<T>, Gas<T>, Extras);
-constexpr int kSweepVariants = 2 * 2 * 2 * 3;
+constexpr int kSweepVariants = 2 * 2 * 2 * 3 * 3;
 
 template <typename T, int DIR, int V>
 constexpr SweepFn<T> sweep_variant() {
   constexpr bool I = V & 1;
   constexpr int GS = (V >> 1) & 1;
   constexpr bool F = (V >> 2) & 1;
-  constexpr int L = V >> 3;
-  if constexpr (DIR == 0)
-    return &k_sweep_x<T, I, GS, L, F>;
+  constexpr int L = (V >> 3) % 3;
+  constexpr int RS = V / 24;
+  if constexpr (RS == 2 && (I || GS))
+    return nullptr;
+  else if constexpr (DIR == 0)
+    return &k_sweep_x<T, I, GS, L, F, RS>;
   else
-    return &k_sweep_y<T, I, GS, L, F>;
+    return &k_sweep_y<T, I, GS, L, F, RS>;
 }
 
 template <typename T, int DIR, int... V>
@@ -564,36 +571,41 @@ SweepFn<T> sweep_table(int v, std::integer_sequence<int, V...>) {
   return table[v];
 }
 
+// The variant for the options; null for an invalid limiter or solver.  With
+// the HLLC flux the instrumentation and the learned guess do not apply.
 template <typename T, int DIR>
-SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter) {
-  const int v = (instr ? 1 : 0) + (guess ? 2 : 0) + (fuse ? 4 : 0) + 8 * limiter;
+SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter, int riemann) {
+  if (limiter < 0 || limiter > 2 || riemann < 0 || riemann > 2) return nullptr;
+  if (riemann == 2) instr = false, guess = 0;
+  const int v = (instr ? 1 : 0) + (guess ? 2 : 0) + (fuse ? 4 : 0) + 8 * limiter + 24 * riemann;
   return sweep_table<T, DIR>(v, std::make_integer_sequence<int, kSweepVariants>());
 }
 
 template <typename T>
 hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  if (G.limiter < 0 || G.limiter > 2) return hipErrorInvalidValue;
-  const SweepFn<T> k = sweep_kernel<T, 0>(instr, guess, ex.fuse != 0, G.limiter);
+  const SweepFn<T> k = sweep_kernel<T, 0>(instr, guess, ex.fuse != 0, G.limiter, G.riemann);
+  if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
                      s, b, G, ex);
   return hipGetLastError();
 }
 
 template <typename T>
-int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter) {
-  if (limiter < 0 || limiter > 2) return 0;
+int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int riemann) {
+  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, fuse, limiter, riemann);
+  if (!k) return 0;
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &nb, sweep_kernel<T, 1>(instr, guess, fuse, limiter), kWave * kWavesPerBlock, 0);
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWave * kWavesPerBlock, 0);
   return e == hipSuccess ? nb : 0;
 }
 
 template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  if (G.limiter < 0 || G.limiter > 2) return hipErrorInvalidValue;
-  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, ex.fuse != 0, G.limiter);
+  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, ex.fuse != 0, G.limiter, G.riemann);
+  if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
                      s, b, G, ex);
   return hipGetLastError();
@@ -648,7 +660,7 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
                                         int, unsigned, hipStream_t);                          \
   template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
                                         int, unsigned, hipStream_t);                          \
-  template int sweep_y_blocks_per_cu<T>(bool, int, bool, int);                                \
+  template int sweep_y_blocks_per_cu<T>(bool, int, bool, int, int);                           \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
   template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);

@@ -40,6 +40,14 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   const double k = std::nearbyint(1.0 / z);
   G.ipow_k = (k >= 1.0 && k <= 64.0 && std::fabs(1.0 / z - k) <= 1e-12 * k) ? (int)k : 0;
   G.limiter = o.limiter;
+  G.riemann = o.riemann;
+  G.g6 = T((g - 1.0) / (g + 1.0));
+  G.two_gp1 = T(2.0 / (g + 1.0));
+  G.half_gp1 = T(0.5 * (g + 1.0));
+  G.rare_coef = T(2.0 / (g - 1.0));
+  // 2/(gamma - 1) (5 for gamma = 1.4): the exact solver's fan density power
+  const double r = std::nearbyint(2.0 / (g - 1.0));
+  G.ipow_r = (r >= 1.0 && r <= 64.0 && std::fabs(2.0 / (g - 1.0) - r) <= 1e-12 * r) ? (int)r : 0;
   return G;
 }
 
@@ -388,8 +396,9 @@ hipError_t Plan::sync_states(std::vector<DevState>& out) {
 namespace {
 
 std::mutex g_tune_mu;
-// keyed by dtype, kernel variant (starting guess, limiter) and grid shapes
-using TuneKey = std::tuple<int, int, int, std::vector<int>>;
+// keyed by dtype, kernel variant (starting guess, limiter, solver) and grid
+// shapes
+using TuneKey = std::tuple<int, int, int, int, std::vector<int>>;
 std::map<TuneKey, LaunchCfg> g_tune_cache;
 
 TuneKey tune_key(const Plan& p) {
@@ -401,7 +410,7 @@ TuneKey tune_key(const Plan& p) {
     shape.push_back(p.bc[g]);
   }
   const int guess = (p.opt.guess == HYDRO_GUESS_MLP && p.mlp) ? 1 : 0;
-  return {p.dtype, guess, p.opt.limiter, shape};
+  return {p.dtype, guess, p.opt.limiter, p.opt.riemann, shape};
 }
 
 }  // namespace
@@ -484,8 +493,10 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
       const bool instr = opt.stats != 0 || log != nullptr;
       const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
       const int bpc = dtype == HYDRO_F64
-                          ? sweep_y_blocks_per_cu<double>(instr, guess, true, opt.limiter)
-                          : sweep_y_blocks_per_cu<float>(instr, guess, true, opt.limiter);
+                          ? sweep_y_blocks_per_cu<double>(instr, guess, true, opt.limiter,
+                                                          opt.riemann)
+                          : sweep_y_blocks_per_cu<float>(instr, guess, true, opt.limiter,
+                                                         opt.riemann);
       const long long slots = (long long)cus * bpc * kWavesPerBlock;
       auto items_for = [&](int sy) {
         long long it = 0;

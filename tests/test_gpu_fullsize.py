@@ -48,16 +48,17 @@ def sample_columns(U):
     return sorted(set(int(c) for c in cols))
 
 
-@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
-def test_fullsize_step(torch_cuda_fs, orc, state, dtype_name):
+@pytest.mark.parametrize("dtype_name,riemann", [("f64", 0), ("f32", 0), ("f64", 1), ("f64", 2)])
+def test_fullsize_step(torch_cuda_fs, orc, state, dtype_name, riemann):
     torch = torch_cuda_fs
     from paper_2106_13465_amd.hydro import Hydro
 
     U = state
-    print(f"fullsize {dtype_name}: 8192^2 one step", flush=True)
-    c = orc.cfg(bc=orc.BC_PERIODIC)
+    print(f"fullsize {dtype_name} solver {riemann}: 8192^2 one step", flush=True)
+    c = orc.cfg(bc=orc.BC_PERIODIC, riemann=riemann)
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     h = Hydro(N, N, 1.4, 0.8, "periodic", dtype=dtype)
+    h.set_options(riemann=riemann)
     h.set_state(U)
     dt_or = orc.compute_dt(U, c)
     if dtype_name == "f64":

@@ -162,6 +162,26 @@ def test_learned_guess_sweep_matches_two_rarefaction(torch_cuda, orc, trained, d
     assert sb["fallbacks"] < 0.25 * sb["interfaces"]
 
 
+def test_learned_guess_with_exact_solver(torch_cuda, orc, trained):
+    """The learned guess as the exact solver's starting point reaches the
+    oracle's exact-solver state (FP64)."""
+    net, _ = trained
+    from paper_2106_13465_amd.hydro import Hydro
+
+    U = inputs.random_states(120, 70, seed=12, rough=0.6)
+    b = Hydro(120, 70, 1.4, 0.8, 3, dtype=torch_cuda.float64)
+    b.set_state(U)
+    b.set_mlp(net)
+    b.set_options(guess=1, stats=1, learned_gate=0.0, riemann=1)
+    b.step(3)
+    ref = U.copy()
+    for _ in range(3):
+        orc.step(ref, orc.cfg(bc=3, riemann=1))
+    assert rel_err(b.get_state(), ref) <= TOL64
+    s = b.stats()
+    assert s["fallbacks"] < 0.25 * s["interfaces"]
+
+
 def test_gate_above_every_jump_is_the_plain_path(torch_cuda, trained):
     """A gate no interface passes: no wave evaluates the network, every
     interface starts from the two-rarefaction guess as in the plain path."""

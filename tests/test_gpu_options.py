@@ -1,7 +1,7 @@
-"""Options beyond the default method: the MC and van Leer limiters and the
-alternating sweep order, each against the FP64 oracle with the same option,
-including graph replay (whose captured sweep order depends on the starting
-step's parity) and the batched path."""
+"""Options beyond the default method: the MC and van Leer limiters, the
+alternating sweep order and the exact / HLLC interface solvers, each against
+the FP64 oracle with the same option, including graph replay (whose captured
+sweep order depends on the starting step's parity) and the batched path."""
 import numpy as np
 import pytest
 
@@ -121,4 +121,120 @@ def test_option_validation(torch_cuda):
     with pytest.raises(HydroError):
         h.set_options(order=2)
     o = h.options()
-    assert o["limiter"] == 0 and o["order"] == 0
+    assert o["limiter"] == 0 and o["order"] == 0 and o["riemann"] == 0
+
+
+# ------------------------------------------------------------------ solvers
+@pytest.mark.parametrize("bc", [1, 2, 3])
+@pytest.mark.parametrize("riemann", [1, 2])
+def test_solvers_fp64(torch_cuda, orc, riemann, bc):
+    U = inputs.random_states(130, 75, seed=300 + 10 * riemann + bc, rough=0.6)
+    h = make(torch_cuda, U, bc, riemann=riemann)
+    h.step(5)
+    t, _, _ = h.clock()
+    ref = U.copy()
+    c = orc.cfg(bc=bc, riemann=riemann)
+    t_or = sum(orc.step(ref, c) for _ in range(5))
+    assert abs(t - t_or) <= 1e-13 * t_or
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("riemann", [1, 2])
+def test_solvers_single_sweeps_fp64(torch_cuda, orc, riemann):
+    """One x- and one y-sweep of a rough state, each against the oracle's."""
+    U = inputs.random_states(97, 66, seed=320 + riemann, rough=0.9)
+    for direction in (0, 1):
+        h = make(torch_cuda, U, 3, riemann=riemann)
+        dt = h.compute_dt()
+        h.sweep(direction)
+        ref = U.copy()
+        orc.sweep(ref, direction, dt, orc.cfg(bc=3, riemann=riemann))
+        assert rel_err(h.get_state(), ref) <= TOL64, direction
+
+
+@pytest.mark.parametrize("riemann", [1, 2])
+def test_solvers_fp32_l1(torch_cuda, orc, riemann):
+    U = inputs.random_smooth(160, 120, seed=330, amp=0.5)
+    h = make(torch_cuda, U, 3, dtype=torch_cuda.float32, riemann=riemann)
+    h.step(10)
+    ref = U.copy()
+    c = orc.cfg(bc=3, riemann=riemann)
+    for _ in range(10):
+        orc.step(ref, c)
+    got = h.get_state().astype(np.float64)
+    for k in range(4):
+        assert np.abs(got[k] - ref[k]).sum() / np.abs(ref[k]).sum() < 1e-5
+
+
+def test_exact_solver_iteration_histogram(torch_cuda, orc):
+    """Newton iteration counts of the exact solver against the oracle's
+    (an integer decided in floating point: within 1% of interfaces)."""
+    U = inputs.random_states(120, 80, seed=340, rough=0.8)
+    h = make(torch_cuda, U, 3, riemann=1, stats=1)
+    h.step(1)
+    s = h.stats()
+    ref = U.copy()
+    hist = np.zeros(11, dtype=np.int64)
+    orc.step(ref, orc.cfg(bc=3, riemann=1), hist)
+    g = np.array(s["hist"][:11])
+    assert g.sum() == hist.sum() > 0
+    assert np.abs(g - hist).sum() <= 0.01 * hist.sum()
+
+
+def test_hllc_counts_nothing(torch_cuda, orc):
+    U = inputs.random_states(64, 40, seed=341, rough=0.5)
+    h = make(torch_cuda, U, 3, riemann=2, stats=1)
+    h.step(2)
+    s = h.stats()
+    assert s["interfaces"] == 0 and sum(s["hist"]) == 0
+
+
+@pytest.mark.parametrize("riemann", [1, 2])
+def test_solvers_with_other_options(torch_cuda, orc, riemann):
+    """Each solver with the MC / van Leer limiters and the alternating
+    order, through graph replays (bitwise equal to eager steps)."""
+    lim = 1 if riemann == 1 else 2
+    U = inputs.random_states(90, 70, seed=350 + riemann, rough=0.6)
+    a = make(torch_cuda, U, 1, riemann=riemann, limiter=lim, order=1)
+    b = make(torch_cuda, U, 1, riemann=riemann, limiter=lim, order=1)
+    a.step(5)
+    b.graph_steps(2)
+    b.graph_steps(3)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    ref = U.copy()
+    c = orc.cfg(bc=1, riemann=riemann, limiter=lim, order=1)
+    for s in range(5):
+        orc.step(ref, c, step_index=s)
+    assert rel_err(a.get_state(), ref) <= TOL64
+
+
+def test_batch_solvers(torch_cuda, orc):
+    from paper_2106_13465_amd.hydro import HydroBatch
+
+    shapes = [(70, 33), (45, 91), (128, 64)]
+    bcs = [2, 3, 1]
+    states = [inputs.random_states(nx, ny, seed=360 + g, rough=0.6)
+              for g, (nx, ny) in enumerate(shapes)]
+    for riemann in (1, 2):
+        b = HydroBatch(shapes, 1.4, 0.8, bcs, dtype=torch_cuda.float64)
+        b.set_options(riemann=riemann)
+        b.set_states(states)
+        b.graph_steps(3)
+        got = b.get_states()
+        for g, U in enumerate(states):
+            ref = U.copy()
+            c = orc.cfg(bc=bcs[g], riemann=riemann)
+            for _ in range(3):
+                orc.step(ref, c)
+            assert rel_err(got[g], ref) <= TOL64, (riemann, g)
+
+
+def test_solver_option_validation(torch_cuda):
+    from paper_2106_13465_amd.hydro import Hydro, HydroError
+
+    h = Hydro(16, 16, 1.4, 0.8, "periodic")
+    with pytest.raises(HydroError):
+        h.set_options(riemann=3)
+    with pytest.raises(HydroError):
+        h.set_options(riemann=2, guess=1)
+    assert h.options()["riemann"] == 0
