@@ -133,17 +133,19 @@ __device__ __forceinline__ Flux<T> euler_flux(T r, T u, T t, T p, const Gas<T>& 
 //     with 1/(p + B) = s^2 (gamma+1)/2 rho_K;
 //   rarefaction: f = 2 c_K/(gamma-1) (y - 1), y = (p/p_K)^z,
 //     f' = (p/p_K)^(z-1)/(rho_K c_K) = y (p_K/p) iz_K, iz_K = 1/(rho_K c_K).
+// y returns (p/p_K)^z on the rarefaction branch (the sampling reuses it).
 template <typename T>
 __device__ __forceinline__ void exact_curve(T p, T ip, T rK, T pK, T cK, T izK, const Gas<T>& G,
-                                            T& f, T& df) {
+                                            T& f, T& df, T& y) {
   if (p > pK) {
     const T a = G.half_gp1 * rK;
     const T s = fm::rsqrt(a * (p + G.g6 * pK));
     f = (p - pK) * s;
     df = s * (T(1) - T(0.5) * (p - pK) * (s * s) * a);
+    y = T(1);
   } else {
     const T x = pK * ip;  // (p/p_K)^-1
-    const T y = G.ipow_k > 0 ? fm::root_inv_full(x, G.ipow_k, G.z) : fm::pow_full(x, -G.z);
+    y = G.ipow_k > 0 ? fm::root_inv_full(x, G.ipow_k, G.z) : fm::pow_full(x, -G.z);
     f = G.rare_coef * cK * (y - T(1));
     df = y * x * izK;
   }
@@ -283,9 +285,9 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     } else {
       // exact f(p) = f_L(p) + f_R(p) + u_R - u_L
       const T ip = fm::rcp(pp);
-      T fL, dL, fR, dR;
-      exact_curve(pp, ip, L.r, L.p, cL, izL, G, fL, dL);
-      exact_curve(pp, ip, R.r, R.p, cR, izR, G, fR, dR);
+      T fL, dL, fR, dR, yL, yR;
+      exact_curve(pp, ip, L.r, L.p, cL, izL, G, fL, dL, yL);
+      exact_curve(pp, ip, R.r, R.p, cR, izR, G, fR, dR, yR);
       dp = -(fL + fR + (R.u - L.u)) * fm::rcp(dL + dR);
     }
     pp = fmax(pp + dp, pmin);
@@ -369,9 +371,9 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   } else {
     // star velocity u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2
     const T ip = fm::rcp(p);
-    T fL, dL, fR, dR;
-    exact_curve(p, ip, L.r, L.p, cL, izL, G, fL, dL);
-    exact_curve(p, ip, R.r, R.p, cR, izR, G, fR, dR);
+    T fL, dL, fR, dR, yL, yR;
+    exact_curve(p, ip, L.r, L.p, cL, izL, G, fL, dL, yL);
+    exact_curve(p, ip, R.r, R.p, cR, izR, G, fR, dR, yR);
     const T us = T(0.5) * (L.u + R.u) + T(0.5) * (fR - fL);
 
     // the exact solution at x/t = 0 on the side of the contact holding it
@@ -397,8 +399,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
         gp = p;
       }
     } else {  // rarefaction: head s u_o - c_o, tail s u* - c_o (p*/p_o)^z
-      const T x = po * ip;  // (p*/p_o)^-1
-      const T y = G.ipow_k > 0 ? fm::root_inv_full(x, G.ipow_k, G.z) : fm::pow_full(x, -G.z);
+      const T y = left ? yL : yR;  // (p*/p_o)^z from the curve at p*
       const T head = uos - co;
       const T tail = uss - co * y;
       if (!(head >= T(0))) {

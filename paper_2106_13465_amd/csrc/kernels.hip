@@ -186,12 +186,14 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 #endif
 constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 learned, then y
 // The exact solver's FP64 y-sweep needs more registers than 3 waves leave
-// (it spilled ~150 bytes per lane there); it asks for 2.
+// (it spilled ~150 bytes per lane there); it asks for 2.  The HLLC FP32
+// y-sweep spilled 68 bytes at 6; it asks for 5.
 template <typename T, int GUESS, int RS>
 struct SweepOcc {
   static constexpr int v = (sizeof(T) == 8 ? 0 : 2) + (GUESS ? 1 : 0);
+  static constexpr int cap = RS == 1 && sizeof(T) == 8 ? 2 : RS == 2 && sizeof(T) == 4 ? 5 : 8;
   static constexpr int x = kOcc[v];
-  static constexpr int y = (RS == 1 && sizeof(T) == 8 && kOcc[4 + v] > 2) ? 2 : kOcc[4 + v];
+  static constexpr int y = kOcc[4 + v] < cap ? kOcc[4 + v] : cap;
 };
 
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS>
