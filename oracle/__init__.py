@@ -40,6 +40,7 @@ class Cfg(ctypes.Structure):
         ("limiter", ctypes.c_int),
         ("order", ctypes.c_int),
         ("riemann", ctypes.c_int),
+        ("nscalars", ctypes.c_int),
     ]
 
 
@@ -78,6 +79,11 @@ def _load():
              ctypes.POINTER(ctypes.c_int)]),
         "oracle_hllc_speeds": (None, [_D, _D, ctypes.c_double, _D]),
         "oracle_hllc_flux": (None, [_D, _D, ctypes.c_double, _D]),
+        "oracle_hllc_left": (ctypes.c_int, [_D, _D, ctypes.c_double]),
+        "oracle_load_pencil_n": (
+            None, [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                   ctypes.c_int, _D]),
+        "oracle_totals_n": (None, [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]),
         "oracle_flux": (None, [_D, ctypes.c_double, _D]),
         "oracle_pencil": (None, [_D, ctypes.c_int, ctypes.c_double, ctypes.POINTER(Cfg), _LL]),
         "oracle_load_pencil": (
@@ -123,9 +129,9 @@ def _vec(x) -> np.ndarray:
 
 
 def cfg(gamma=1.4, cfl=0.8, bc=BC_PERIODIC, niter=10, tol=1e-8, limiter=LIMITER_MINMOD,
-        order=ORDER_XY, riemann=RIEMANN_TWO_SHOCK) -> Cfg:
+        order=ORDER_XY, riemann=RIEMANN_TWO_SHOCK, nscalars=0) -> Cfg:
     return Cfg(float(gamma), float(cfl), int(bc), int(niter), float(tol), int(limiter),
-               int(order), int(riemann))
+               int(order), int(riemann), int(nscalars))
 
 
 # ---------------------------------------------------------------- single steps
@@ -205,6 +211,11 @@ def hllc_speeds(qL, qR, gamma=1.4) -> np.ndarray:
     return S
 
 
+def hllc_left(qL, qR, gamma=1.4) -> bool:
+    qL, qR = _vec(qL), _vec(qR)
+    return bool(_load().oracle_hllc_left(_dptr(qL), _dptr(qR), gamma))
+
+
 def hllc_flux(qL, qR, gamma=1.4) -> np.ndarray:
     qL, qR = _vec(qL), _vec(qR)
     F = np.zeros(4)
@@ -221,9 +232,11 @@ def flux(qg, gamma=1.4) -> np.ndarray:
 
 # ---------------------------------------------------------------- pencils, grids
 def pencil(w: np.ndarray, lam: float, c: Cfg, hist: np.ndarray | None = None) -> np.ndarray:
-    """1D update of a pencil held with its ghosts, w of shape [4, n+4]; returns
-    the updated copy."""
+    """1D update of a pencil held with its ghosts, w of shape [4 + c.nscalars,
+    n+4]; returns the updated copy."""
     w = np.ascontiguousarray(w, dtype=np.float64).copy()
+    if w.shape[0] != 4 + c.nscalars:
+        raise ValueError("pencil rows must be 4 + nscalars")
     n = w.shape[1] - 4
     hp = hist.ctypes.data_as(_LL) if hist is not None else None
     _load().oracle_pencil(_dptr(w), n, lam, ctypes.byref(c), hp)
@@ -232,23 +245,25 @@ def pencil(w: np.ndarray, lam: float, c: Cfg, hist: np.ndarray | None = None) ->
 
 def load_pencil(U: np.ndarray, direction: int, line: int, bc: int) -> np.ndarray:
     U = np.ascontiguousarray(U, dtype=np.float64)
-    _, ny, nx = U.shape
+    nv, ny, nx = U.shape
     n = nx if direction == DIR_X else ny
-    w = np.zeros((4, n + 4))
-    _load().oracle_load_pencil(_dptr(U), nx, ny, direction, line, bc, _dptr(w))
+    w = np.zeros((nv, n + 4))
+    _load().oracle_load_pencil_n(_dptr(U), nx, ny, nv, direction, line, bc, _dptr(w))
     return w
 
 
-def _grid(U: np.ndarray) -> np.ndarray:
-    if U.dtype != np.float64 or not U.flags.c_contiguous or U.ndim != 3 or U.shape[0] != 4:
-        raise ValueError("oracle grids are contiguous float64 arrays [4, ny, nx]")
+def _grid(U: np.ndarray, c: Cfg | None = None) -> np.ndarray:
+    nv = 4 + (c.nscalars if c is not None else 0)
+    ok = U.dtype == np.float64 and U.flags.c_contiguous and U.ndim == 3
+    if not ok or (U.shape[0] != nv if c is not None else U.shape[0] < 4):
+        raise ValueError("oracle grids are contiguous float64 arrays [4 + nscalars, ny, nx]")
     return U
 
 
 def sweep(U: np.ndarray, direction: int, dt: float, c: Cfg,
           hist: np.ndarray | None = None) -> None:
-    """In-place directional sweep of U [4, ny, nx]."""
-    _grid(U)
+    """In-place directional sweep of U [4 + c.nscalars, ny, nx]."""
+    _grid(U, c)
     _, ny, nx = U.shape
     hp = hist.ctypes.data_as(_LL) if hist is not None else None
     _load().oracle_sweep(_dptr(U), nx, ny, direction, dt, ctypes.byref(c), hp)
@@ -269,17 +284,18 @@ def compute_dt(U: np.ndarray, c: Cfg) -> float:
 def step(U: np.ndarray, c: Cfg, hist: np.ndarray | None = None, step_index: int = 0) -> float:
     """In-place time step (dt, then the two sweeps in the order c.order gives
     for step number step_index); returns dt."""
-    _grid(U)
+    _grid(U, c)
     _, ny, nx = U.shape
     hp = hist.ctypes.data_as(_LL) if hist is not None else None
     return _load().oracle_step_n(_dptr(U), nx, ny, ctypes.byref(c), int(step_index), hp)
 
 
 def totals(U: np.ndarray) -> np.ndarray:
+    """Totals of every plane of U (4 conserved variables, then the scalars)."""
     _grid(U)
-    _, ny, nx = U.shape
-    out = np.zeros(4)
-    _load().oracle_totals(_dptr(U), nx, ny, _dptr(out))
+    nv, ny, nx = U.shape
+    out = np.zeros(nv)
+    _load().oracle_totals_n(_dptr(U), nx, ny, nv, _dptr(out))
     return out
 
 

@@ -440,6 +440,14 @@ void oracle_hllc_flux(const double qL[4], const double qR[4], double gamma,
   for (int k = 0; k < 4; k++) F[k] = F[k] + SK * (Us[k] - U[k]);
 }
 
+int oracle_hllc_left(const double qL[4], const double qR[4], double gamma) {
+  double S[3];
+  oracle_hllc_speeds(qL, qR, gamma, S);
+  if (S[0] >= 0.0) return 1;
+  if (S[2] <= 0.0) return 0;
+  return S[1] >= 0.0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One pencil (Figure 5: READ into a 1D buffer, COMPUTE, WRITE back).          */
 /* ------------------------------------------------------------------------ */
@@ -447,10 +455,12 @@ void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
                    long long *hist) {
   const double g = c->gamma;
   const int m = n + 4; /* cells -2 .. n+1 */
+  const int ns = c->nscalars;
   double *q = (double *)malloc(sizeof(double) * 4 * (size_t)m);
   double *qm = (double *)malloc(sizeof(double) * 4 * (size_t)m);
   double *qp = (double *)malloc(sizeof(double) * 4 * (size_t)m);
   double *F = (double *)malloc(sizeof(double) * 4 * (size_t)m);
+  int *left = (int *)malloc(sizeof(int) * (size_t)m);
 
   /* primitive variables of cells -2 .. n+1 */
   for (int j = 0; j < m; j++) {
@@ -466,31 +476,62 @@ void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
     oracle_trace(&q[4 * j], dq, g, lam, &qm[4 * j], &qp[4 * j]);
   }
   /* Riemann problem and flux at interfaces -1/2 .. n-1/2: interface between
-   * pencil columns j and j+1 is stored at F[j] */
+   * pencil columns j and j+1 is stored at F[j]; left[j] says whether x/t = 0
+   * lies on the left of the contact there */
   for (int j = 1; j < m - 2; j++) {
     if (c->riemann == ORACLE_RIEMANN_HLLC) { /* no iteration to count */
       oracle_hllc_flux(&qp[4 * j], &qm[4 * (j + 1)], g, &F[4 * j]);
+      left[j] = oracle_hllc_left(&qp[4 * j], &qm[4 * (j + 1)], g);
       continue;
     }
-    double qg[4];
+    double qg[4], us;
     int conv;
     int it = c->riemann == ORACLE_RIEMANN_EXACT
                  ? oracle_riemann_exact(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter,
-                                        c->tol, qg, NULL, NULL, &conv)
+                                        c->tol, qg, NULL, &us, &conv)
                  : oracle_riemann(&qp[4 * j], &qm[4 * (j + 1)], g, c->niter, c->tol,
-                                  qg, NULL, NULL, &conv);
+                                  qg, NULL, &us, &conv);
     if (hist) hist[conv ? it : 0]++;
     oracle_flux(qg, g, &F[4 * j]);
+    left[j] = us >= 0.0;
   }
   /* conservative update of cells 0 .. n-1 (columns 2 .. n+1) */
   for (int j = 2; j < m - 2; j++)
     for (int k = 0; k < 4; k++)
       w[k * m + j] = w[k * m + j] + lam * (F[4 * (j - 1) + k] - F[4 * j + k]);
 
+  /* passive scalars (rows 4.. of w hold rho X): X = (rho X)/rho with the
+   * floored density of the primitive variables, limited slopes, faces
+   * X -/+ dX/2 + (dt/h) S_X/2 with the advective source S_X = -u dX, and the
+   * flux of rho X = mass flux times the face value X on the side of the
+   * contact that holds x/t = 0 (reading: the scalar is carried by the
+   * contact, like the transverse velocity) */
+  for (int s = 0; s < ns; s++) {
+    double *ws = w + (size_t)(4 + s) * m;
+    double *X = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Xm = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Xp = (double *)malloc(sizeof(double) * (size_t)m);
+    double *FX = (double *)malloc(sizeof(double) * (size_t)m);
+    for (int j = 0; j < m; j++) X[j] = ws[j] / q[4 * j];
+    for (int j = 1; j < m - 1; j++) {
+      double dX = oracle_limit(X[j] - X[j - 1], X[j + 1] - X[j], c->limiter);
+      double half_step = 0.5 * lam * (-q[4 * j + 1] * dX);
+      Xm[j] = X[j] - 0.5 * dX + half_step;
+      Xp[j] = X[j] + 0.5 * dX + half_step;
+    }
+    for (int j = 1; j < m - 2; j++) FX[j] = F[4 * j] * (left[j] ? Xp[j] : Xm[j + 1]);
+    for (int j = 2; j < m - 2; j++) ws[j] = ws[j] + lam * (FX[j - 1] - FX[j]);
+    free(X);
+    free(Xm);
+    free(Xp);
+    free(FX);
+  }
+
   free(q);
   free(qm);
   free(qp);
   free(F);
+  free(left);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -507,14 +548,19 @@ static long cell_index(int nx, int dir, int line, int i) {
   return dir == ORACLE_DIR_X ? (long)line * nx + i : (long)i * nx + line;
 }
 
-void oracle_load_pencil(const double *U, int nx, int ny, int dir, int line,
-                        int bc, double *w) {
+/* grid plane of pencil variable k: rho, normal momentum, transverse
+ * momentum, E, then the passive scalars in their own order */
+static int pencil_plane(int dir, int k) {
+  if (k == 1) return dir == ORACLE_DIR_X ? 1 : 2;
+  if (k == 2) return dir == ORACLE_DIR_X ? 2 : 1;
+  return k;
+}
+
+void oracle_load_pencil_n(const double *U, int nx, int ny, int nvars, int dir,
+                          int line, int bc, double *w) {
   const int n = dir == ORACLE_DIR_X ? nx : ny;
   const int m = n + 4;
   const long plane = (long)nx * ny;
-  /* conserved variable order in the pencil: rho, normal, transverse, E */
-  const int vmap[4] = {0, dir == ORACLE_DIR_X ? 1 : 2,
-                       dir == ORACLE_DIR_X ? 2 : 1, 3};
   for (int j = 0; j < m; j++) {
     int i = j - 2;
     double sign = 1.0;
@@ -530,11 +576,16 @@ void oracle_load_pencil(const double *U, int nx, int ny, int dir, int line,
       }
     }
     long off = cell_index(nx, dir, line, i);
-    for (int k = 0; k < 4; k++) {
-      double v = U[vmap[k] * plane + off];
+    for (int k = 0; k < nvars; k++) {
+      double v = U[pencil_plane(dir, k) * plane + off];
       w[k * m + j] = k == 1 ? sign * v : v;
     }
   }
+}
+
+void oracle_load_pencil(const double *U, int nx, int ny, int dir, int line,
+                        int bc, double *w) {
+  oracle_load_pencil_n(U, nx, ny, 4, dir, line, bc, w);
 }
 
 void oracle_sweep(double *U, int nx, int ny, int dir, double dt,
@@ -542,22 +593,21 @@ void oracle_sweep(double *U, int nx, int ny, int dir, double dt,
   const int n = dir == ORACLE_DIR_X ? nx : ny;
   const int lines = dir == ORACLE_DIR_X ? ny : nx;
   const int m = n + 4;
+  const int nv = 4 + c->nscalars;
   const long plane = (long)nx * ny;
   const double h = 1.0 / (double)(nx > ny ? nx : ny);
   const double lam = dt / h;
-  const int vmap[4] = {0, dir == ORACLE_DIR_X ? 1 : 2,
-                       dir == ORACLE_DIR_X ? 2 : 1, 3};
 
   /* Pencils are independent (Section 1), so they may run in any order;
    * the result does not depend on the thread count. */
 #pragma omp parallel for schedule(static) if (hist == NULL)
   for (int line = 0; line < lines; line++) {
-    double *w = (double *)malloc(sizeof(double) * 4 * (size_t)m);
-    oracle_load_pencil(U, nx, ny, dir, line, c->bc, w);
+    double *w = (double *)malloc(sizeof(double) * (size_t)nv * (size_t)m);
+    oracle_load_pencil_n(U, nx, ny, nv, dir, line, c->bc, w);
     oracle_pencil(w, n, lam, c, hist);
     for (int i = 0; i < n; i++) {
       long off = cell_index(nx, dir, line, i);
-      for (int k = 0; k < 4; k++) U[vmap[k] * plane + off] = w[k * m + i + 2];
+      for (int k = 0; k < nv; k++) U[pencil_plane(dir, k) * plane + off] = w[k * m + i + 2];
     }
     free(w);
   }
@@ -606,10 +656,10 @@ double oracle_step(double *U, int nx, int ny, const oracle_cfg *c,
 /* Conserved totals: sum of U_k h^2 over interior cells, Neumaier-compensated */
 /* so that the oracle's own rounding stays a few ulp.                          */
 /* ------------------------------------------------------------------------ */
-void oracle_totals(const double *U, int nx, int ny, double out[4]) {
+void oracle_totals_n(const double *U, int nx, int ny, int nvars, double *out) {
   const long plane = (long)nx * ny;
   const double h = 1.0 / (double)(nx > ny ? nx : ny);
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < nvars; k++) {
     double sum = 0.0, comp = 0.0;
     for (long off = 0; off < plane; off++) {
       double x = U[k * plane + off];
@@ -622,6 +672,10 @@ void oracle_totals(const double *U, int nx, int ny, double out[4]) {
     }
     out[k] = (sum + comp) * (h * h);
   }
+}
+
+void oracle_totals(const double *U, int nx, int ny, double out[4]) {
+  oracle_totals_n(U, nx, ny, 4, out);
 }
 
 int oracle_threads(void) {

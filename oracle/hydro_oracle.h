@@ -25,11 +25,12 @@
  * two-rarefaction guess, linear fan sampling, CFL time step).  Every reading
  * is listed next to the function that takes it.  Options beyond them: the
  * MC and van Leer limiters, and sweep orders that alternate x-y / y-x
- * between steps (Strang-type symmetrisation of the splitting), and two other
- * interface solvers: the exact Riemann solver and the HLLC flux.
+ * between steps (Strang-type symmetrisation of the splitting), two other
+ * interface solvers (the exact Riemann solver and the HLLC flux), and
+ * passive scalars advected with the flow.
  *
- * Layout: a grid is double U[4][ny][nx] (x fastest), variables
- * (rho, rho*u, rho*v, E).  Pencils are rows (x-sweep) or columns (y-sweep).
+ * Layout: a grid is double U[4 + nscalars][ny][nx] (x fastest), variables
+ * (rho, rho*u, rho*v, E) and then rho*X for each passive scalar X.  Pencils are rows (x-sweep) or columns (y-sweep).
  * Cells are square, h = 1 / max(nx, ny).
  */
 #ifndef HYDRO_ORACLE_H
@@ -59,6 +60,8 @@ extern "C" {
 #define ORACLE_RIEMANN_EXACT 1     /* Newton on the exact wave curves */
 #define ORACLE_RIEMANN_HLLC 2      /* HLLC flux, Einfeldt wave speeds */
 
+#define ORACLE_MAX_SCALARS 4
+
 #define ORACLE_ORDER_XY 0         /* x-sweep then y-sweep every step */
 #define ORACLE_ORDER_ALTERNATE 1  /* x then y on even steps, y then x on odd */
 
@@ -71,6 +74,7 @@ typedef struct {
   int limiter;  /* ORACLE_LIMITER_* (minmod) */
   int order;    /* ORACLE_ORDER_* (x then y) */
   int riemann;  /* ORACLE_RIEMANN_* (two-shock) */
+  int nscalars; /* passive scalars carried after E (0..ORACLE_MAX_SCALARS) */
 } oracle_cfg;
 
 /* conservative (rho, m_n, m_t, E) -> primitive (rho, u_n, u_t, p), floored */
@@ -129,13 +133,16 @@ void oracle_hllc_speeds(const double qL[4], const double qR[4], double gamma,
 /* HLLC flux through the interface between primitive states qL and qR */
 void oracle_hllc_flux(const double qL[4], const double qR[4], double gamma,
                       double F[4]);
+/* 1 when x/t = 0 lies left of the HLLC contact (S_L >= 0, or S_R > 0 and
+ * S* >= 0) */
+int oracle_hllc_left(const double qL[4], const double qR[4], double gamma);
 
 /* Euler flux normal to the interface from the Godunov state */
 void oracle_flux(const double qg[4], double gamma, double F[4]);
 
-/* 1D update of one pencil held with its ghost cells: w is [4][n+4], cell i of
- * the pencil at column i+2 (ghosts at 0,1 and n+2,n+3), variables
- * (rho, m_n, m_t, E).  Cells 0..n-1 are updated in place with
+/* 1D update of one pencil held with its ghost cells: w is [4+nscalars][n+4],
+ * cell i of the pencil at column i+2 (ghosts at 0,1 and n+2,n+3), variables
+ * (rho, m_n, m_t, E, rho X_1, ...).  Cells 0..n-1 are updated in place with
  * lambda = dt/h.  hist (may be NULL) has niter+1 slots: hist[k] counts
  * interfaces converged after k iterations, hist[0] the unconverged ones (the
  * HLLC flux iterates nothing and counts nothing). */
@@ -143,9 +150,13 @@ void oracle_pencil(double *w, int n, double lam, const oracle_cfg *c,
                    long long *hist);
 
 /* copy pencil `line` of direction dir out of U into w ([4][n+4]) and fill
- * its two ghost cells per side by the boundary rule */
+ * its two ghost cells per side by the boundary rule (scalars are copied like
+ * density: only the normal momentum changes sign at a wall) */
 void oracle_load_pencil(const double *U, int nx, int ny, int dir, int line,
                         int bc, double *w);
+/* the same for nvars = 4 + nscalars planes, w [nvars][n+4] */
+void oracle_load_pencil_n(const double *U, int nx, int ny, int nvars, int dir,
+                          int line, int bc, double *w);
 
 /* one directional sweep of the whole grid with time step dt */
 void oracle_sweep(double *U, int nx, int ny, int dir, double dt,
@@ -166,6 +177,8 @@ double oracle_step_n(double *U, int nx, int ny, const oracle_cfg *c,
 
 /* sum over interior cells of each conserved variable times h^2 */
 void oracle_totals(const double *U, int nx, int ny, double out[4]);
+/* the same for nvars planes (4 + passive scalars) */
+void oracle_totals_n(const double *U, int nx, int ny, int nvars, double *out);
 
 /* number of OpenMP threads the sweeps use (1 when built without OpenMP) */
 int oracle_threads(void);

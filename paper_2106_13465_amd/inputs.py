@@ -239,3 +239,28 @@ def quadrant_batch(ngrids: int = 64, seed: int = SEED_BASE + 4, nmin: int = 512,
         quad[half:, half:] = 3
         grids.append(conservative(rho_q[quad], u_q[quad], v_q[quad], p_q[quad], gamma))
     return grids
+
+
+def with_scalars(U: np.ndarray, X) -> np.ndarray:
+    """Append passive-scalar planes rho * X_k to a conservative state
+    [4, ny, nx]; X is one field [ny, nx] or a stack [k, ny, nx]."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 2:
+        X = X[None]
+    return np.ascontiguousarray(np.concatenate([U, U[0][None] * X], axis=0))
+
+
+def random_scalars(nx: int, ny: int, seed: int, k: int = 1) -> np.ndarray:
+    """k seeded scalar fields [k, ny, nx]: a smooth part plus cell noise, with
+    values of both signs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = cell_size(nx, ny)
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    Xg, Yg = np.meshgrid(x, y)
+    out = np.empty((k, ny, nx))
+    for s in range(k):
+        kx, ky = rng.integers(1, 4, size=2)
+        out[s] = (np.sin(2 * np.pi * (kx * Xg + ky * Yg) + rng.uniform(0, 2 * np.pi))
+                  + 0.3 * rng.uniform(-1, 1, size=(ny, nx)))
+    return out
