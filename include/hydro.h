@@ -19,9 +19,11 @@
  * linear sampling across rarefaction fans; CFL time step
  * dt = cfl * h / max(|u|+c, |v|+c); floors rho >= 1e-10, c >= 1e-10.
  *
- * STATE LAYOUT.  U is a caller-owned device array [4][ny][pitch] of float64
- * (HYDRO_F64) or float32 (HYDRO_F32): planes rho, rho*u, rho*v, E; x is the
- * fastest index, pitch >= nx elements (a multiple of 64 keeps rows aligned).
+ * STATE LAYOUT.  U is a caller-owned device array [4 + ns][ny][pitch] of
+ * float64 (HYDRO_F64) or float32 (HYDRO_F32): planes rho, rho*u, rho*v, E,
+ * then rho*X for each of the ns passive scalars X (hydro_set_scalars; 0 by
+ * default); x is the fastest index, pitch >= nx elements (a multiple of 64
+ * keeps rows aligned).
  * Interior cells only: ghost cells never live in user memory.  Cells are
  * square, h = 1 / max(nx, ny).  The library never frees caller memory.
  * Sweeps are out of place: the handle owns a second buffer of the same size
@@ -66,6 +68,7 @@ enum {
 };
 
 #define HYDRO_MAX_NITER 32
+#define HYDRO_MAX_SCALARS 1
 
 #define HYDRO_LEARNED_GATE_DEFAULT 1.0
 
@@ -146,6 +149,14 @@ void hydro_destroy(hydro_t *h);
 /* Message of the last failed call on this thread ("" if none). */
 const char *hydro_last_error(void);
 
+/* Carry n passive scalars (0..HYDRO_MAX_SCALARS): quantities X advected with
+ * the flow and conserved as rho X, stored after E.  Each is reconstructed
+ * like the primitive variables (same limiter, MUSCL-Hancock faces with the
+ * advective source -u dX) and crosses an interface with the mass flux, at the
+ * value of the side of the contact that holds x/t = 0.  They do not act on
+ * the flow.  Only before hydro_bind (HYDRO_ESTATE after). */
+int hydro_set_scalars(hydro_t *h, int n);
+
 /* Bind the state U (device pointer, layout above, pitch in elements) of type
  * dtype and the HIP stream (hipStream_t; NULL = default stream) all later
  * work runs on.  Rebinding is allowed; it invalidates the fused max speed, so
@@ -177,10 +188,10 @@ int hydro_sweep(hydro_t *h, int dir);
  * Asynchronous, no host synchronisation. */
 int hydro_step(hydro_t *h);
 
-/* out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E), summed in
- * FP64 in a fixed order (deterministic), also for float32 states.
- * Synchronises the stream. */
-int hydro_conserved_totals(hydro_t *h, double out[4]);
+/* out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E, then the
+ * passive scalars' rho X: 4 + ns values), summed in FP64 in a fixed order
+ * (deterministic), also for float32 states.  Synchronises the stream. */
+int hydro_conserved_totals(hydro_t *h, double *out);
 
 /* Simulated time, steps taken and the last dt (device clock).  Synchronises. */
 int hydro_get_clock(hydro_t *h, double *t, long *step, double *dt);
@@ -276,8 +287,9 @@ long long hydro_logger_count(hydro_t *h);
  * Same numerics and readings as a single grid.
  *
  * LAYOUT.  All grids live in one caller-owned device buffer; grid g occupies
- * [offsets[g], offsets[g] + 4 * ny[g] * pitches[g]) elements with the layout
- * of a single grid ([4][ny][pitch], x fastest).  hydro_batch_layout gives the
+ * [offsets[g], offsets[g] + (4 + ns) * ny[g] * pitches[g]) elements with the
+ * layout of a single grid ([4 + ns][ny][pitch], x fastest; ns passive
+ * scalars, hydro_batch_set_scalars).  hydro_batch_layout gives the
  * offsets and pitches the library uses (rows padded to 256 bytes).
  * ------------------------------------------------------------------------ */
 typedef struct hydro_batch_s hydro_batch_t;
@@ -294,6 +306,9 @@ long long hydro_batch_layout(const hydro_batch_t *b, int dtype, long long *offse
  * buffer. */
 int hydro_batch_bind(hydro_batch_t *b, void *U, int dtype, void *hip_stream);
 int hydro_batch_set_options(hydro_batch_t *b, const hydro_options_t *o);
+/* Passive scalars of every grid, as hydro_set_scalars: before binding (and
+ * before hydro_batch_layout, whose sizes include them). */
+int hydro_batch_set_scalars(hydro_batch_t *b, int n);
 int hydro_batch_invalidate(hydro_batch_t *b);
 /* Per-grid dt into dt[n] (may be NULL); synchronises. */
 int hydro_batch_compute_dt(hydro_batch_t *b, double *dt);
@@ -301,7 +316,7 @@ int hydro_batch_compute_dt(hydro_batch_t *b, double *dt);
 int hydro_batch_step(hydro_batch_t *b);
 /* nsteps steps of every grid as one replay of a captured HIP graph. */
 int hydro_batch_graph_steps(hydro_batch_t *b, int nsteps);
-/* out[4 g + k]: totals of grid g; synchronises. */
+/* out[(4 + ns) g + k]: totals of grid g; synchronises. */
 int hydro_batch_totals(hydro_batch_t *b, double *out);
 /* Per-grid clocks (arrays of n, any may be NULL); synchronises. */
 int hydro_batch_get_clock(hydro_batch_t *b, double *t, long *step, double *dt);

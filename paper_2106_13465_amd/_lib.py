@@ -46,6 +46,7 @@ HYDRO_LEARNED_GATE_DEFAULT = 1.0
 HYDRO_LIMITER_MINMOD, HYDRO_LIMITER_MC, HYDRO_LIMITER_VANLEER = 0, 1, 2
 HYDRO_ORDER_XY, HYDRO_ORDER_ALTERNATE = 0, 1
 HYDRO_RIEMANN_TWO_SHOCK, HYDRO_RIEMANN_EXACT, HYDRO_RIEMANN_HLLC = 0, 1, 2
+HYDRO_MAX_SCALARS = 1
 
 
 class hydro_stats_t(ctypes.Structure):
@@ -93,6 +94,7 @@ SIGNATURES = {
     "hydro_sweep": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_step": (ctypes.c_int, [_vp]),
     "hydro_conserved_totals": (ctypes.c_int, [_vp, _D]),
+    "hydro_set_scalars": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_get_clock": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_long), _D]),
     "hydro_set_clock": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long]),
     "hydro_riemann_stats": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_stats_t), ctypes.c_int]),
@@ -119,6 +121,7 @@ SIGNATURES = {
     "hydro_batch_layout": (ctypes.c_longlong, [_vp, ctypes.c_int, _LL, _L]),
     "hydro_batch_bind": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
     "hydro_batch_set_options": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_options_t)]),
+    "hydro_batch_set_scalars": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_batch_invalidate": (ctypes.c_int, [_vp]),
     "hydro_batch_compute_dt": (ctypes.c_int, [_vp, _D]),
     "hydro_batch_step": (ctypes.c_int, [_vp]),

@@ -190,8 +190,18 @@ int do_totals(hydro::Plan* p, double* out) {
   std::vector<hydro::DevState> s;
   rc = sync_states(p, s);
   if (rc) return rc;
+  const int nv = 4 + p->nscalars;
   for (int i = 0; i < p->n; ++i)
-    for (int k = 0; k < 4; ++k) out[4 * i + k] = s[i].totals[k];
+    for (int k = 0; k < nv; ++k) out[nv * i + k] = s[i].totals[k];
+  return HYDRO_OK;
+}
+
+int do_set_scalars(hydro::Plan* p, int n) {
+  if (!p) return fail(HYDRO_EINVAL, "NULL handle");
+  if (n < 0 || n > HYDRO_MAX_SCALARS)
+    return fail(HYDRO_EINVAL, "%d passive scalars: must be in 0..%d", n, HYDRO_MAX_SCALARS);
+  if (p->bound) return fail(HYDRO_ESTATE, "passive scalars must be set before binding");
+  p->nscalars = n;
   return HYDRO_OK;
 }
 
@@ -401,7 +411,9 @@ int hydro_sweep(hydro_t* h, int dir) {
 
 int hydro_step(hydro_t* h) { return do_step(h); }
 int hydro_graph_steps(hydro_t* h, int nsteps) { return do_graph_steps(h, nsteps); }
-int hydro_conserved_totals(hydro_t* h, double out[4]) { return do_totals(h, out); }
+int hydro_conserved_totals(hydro_t* h, double* out) { return do_totals(h, out); }
+
+int hydro_set_scalars(hydro_t* h, int n) { return do_set_scalars(h, n); }
 
 int hydro_get_clock(hydro_t* h, double* t, long* step, double* dt) {
   return do_get_clock(h, t, step, dt);
@@ -444,7 +456,7 @@ long long hydro_batch_layout(const hydro_batch_t* b, int dtype, long long* offse
     const long p = hydro::padded_pitch(b->nx[g], dtype);
     if (offsets) offsets[g] = total;
     if (pitches) pitches[g] = p;
-    total += 4LL * p * b->ny[g];
+    total += (4LL + b->nscalars) * p * b->ny[g];
   }
   return total;
 }
@@ -462,6 +474,8 @@ int hydro_batch_bind(hydro_batch_t* b, void* U, int dtype, void* hip_stream) {
 int hydro_batch_set_options(hydro_batch_t* b, const hydro_options_t* o) {
   return do_set_options(b, o);
 }
+
+int hydro_batch_set_scalars(hydro_batch_t* b, int n) { return do_set_scalars(b, n); }
 
 int hydro_batch_invalidate(hydro_batch_t* b) {
   if (!b) return fail(HYDRO_EINVAL, "NULL handle");

@@ -7,7 +7,8 @@
 // state lives at offset GridDesc::off of two equally laid-out buffers; its
 // variable plane v of cell (x, y) is at off + v * plane + y * pitch + x.  A
 // sweep reads one buffer and writes the other, so no wave ever reads a cell
-// another wave has already updated.
+// another wave has already updated.  Planes 0..3 are rho, rho u, rho v, E;
+// planes 4.. hold rho X for the passive scalars X.
 #pragma once
 #include <stdint.h>
 
@@ -20,6 +21,8 @@ constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kXOut = kWave - 4;  // x-sweep cells updated per 64-lane segment
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxTotBlocks = 512;  // partial-sum blocks per grid for totals
+constexpr int kMaxScalars = 1;      // passive scalars (HYDRO_MAX_SCALARS)
+constexpr int kMaxVars = 4 + kMaxScalars;
 
 // status word bits
 constexpr int kStatusNonPhys = 1;
@@ -32,7 +35,7 @@ struct DevState {
   unsigned long long acc;  // running max wave speed: bits of a double >= 0
   int status;       // kStatus* bits, latched
   int pad0;
-  double totals[4];
+  double totals[kMaxVars];
   unsigned long long interfaces;          // Riemann problems counted
   unsigned long long hist[kMaxIter + 1];  // [0] unconverged, [k] k iterations
   unsigned long long fallbacks;           // learned guesses rejected
@@ -81,6 +84,7 @@ struct Batch {
   DevState* st;       // device array [ngrids]
   int ngrids;
   int seg;            // x-sweep: 60-cell segments per wave item; y-sweep: rows per item
+  int nv;             // variable planes per grid: 4 + passive scalars
   long long items;    // waves (sweeps) or rows (row kernels) over the whole batch
 };
 

@@ -161,7 +161,7 @@ __device__ __forceinline__ void exact_curve(T p, T ip, T rK, T pK, T cK, T izK, 
 //   U*_K = m_K/(S_K - S*) (1, S*, v_K, E_K/rho_K + (S* - u_K)(S* + p_K/m_K)).
 template <typename T>
 __device__ __forceinline__ Flux<T> hllc_flux(const Prim<T>& L, const Prim<T>& R,
-                                             const Gas<T>& G) {
+                                             const Gas<T>& G, bool& left_out) {
   const T qL = fm::rsqrt(L.r), qR = fm::rsqrt(R.r);  // 1/sqrt(rho)
   const T irL = qL * qL, irR = qR * qR;
   const T wL = L.r * qL, wR = R.r * qR;  // sqrt(rho)
@@ -179,6 +179,7 @@ __device__ __forceinline__ Flux<T> hllc_flux(const Prim<T>& L, const Prim<T>& R,
 
   const bool outL = SL >= T(0), outR = SR <= T(0);
   const bool left = outL || (!outR && Ss >= T(0));
+  left_out = left;
   const T r = left ? L.r : R.r, u = left ? L.u : R.u, t = left ? L.t : R.t, p = left ? L.p : R.p;
   Flux<T> F = euler_flux(r, u, t, p, G);
   if (!outL && !outR) {
@@ -204,18 +205,20 @@ __device__ __forceinline__ Flux<T> hllc_flux(const Prim<T>& L, const Prim<T>& R,
 // two-rarefaction guess with the full cap (fell_back).  p_learned < 0 means a
 // learned guess was produced but is unusable (also a fall-back); 0 means no
 // learned guess.  iters counts all iterations; pstar returns the final star
-// pressure.
+// pressure; left says whether x/t = 0 lies left of the contact (the side
+// whose passive scalars cross the interface).
 template <int RS, typename T>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
                                                 const Gas<T>& G, T p_learned, int& iters,
-                                                bool& converged, bool& fell_back, T& pstar) {
+                                                bool& converged, bool& fell_back, T& pstar,
+                                                bool& left_out) {
   if constexpr (RS == 2) {
     (void)p_learned;
     iters = 0;
     converged = true;
     fell_back = false;
     pstar = T(0);
-    return hllc_flux(L, R, G);
+    return hllc_flux(L, R, G, left_out);
   } else {
   T irL, irR, ipL, ipR;
   if constexpr (sizeof(T) == 8) {
@@ -330,6 +333,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
 
     // upwind side of the contact (u* = 0 -> left)
     const bool left = us >= T(0);
+    left_out = left;
     const T ro = left ? L.r : R.r;
     const T uo = left ? L.u : R.u;
     to = left ? L.t : R.t;
@@ -380,6 +384,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     // (u* = 0 -> left), written for the left side with the right side
     // mirrored (s u for each velocity u, s = -1 on the right)
     const bool left = us >= T(0);
+    left_out = left;
     const T ro = left ? L.r : R.r;
     const T uo = left ? L.u : R.u;
     to = left ? L.t : R.t;

@@ -187,17 +187,20 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 learned, then y
 // The exact solver's FP64 y-sweep needs more registers than 3 waves leave
 // (it spilled ~150 bytes per lane there); it asks for 2.  The HLLC FP32
-// y-sweep spilled 68 bytes at 6; it asks for 5.
-template <typename T, int GUESS, int RS>
+// y-sweep spilled 68 bytes at 6, the FP32 sweeps with a passive scalar 40-50;
+// they ask for 5.
+template <typename T, int GUESS, int RS, int NS>
 struct SweepOcc {
-  static constexpr int v = (sizeof(T) == 8 ? 0 : 2) + (GUESS ? 1 : 0);
-  static constexpr int cap = RS == 1 && sizeof(T) == 8 ? 2 : RS == 2 && sizeof(T) == 4 ? 5 : 8;
-  static constexpr int x = kOcc[v];
-  static constexpr int y = kOcc[4 + v] < cap ? kOcc[4 + v] : cap;
+  static constexpr bool f32 = sizeof(T) == 4;
+  static constexpr int v = (f32 ? 2 : 0) + (GUESS ? 1 : 0);
+  static constexpr int cap_x = f32 && NS > 0 ? 5 : 8;
+  static constexpr int cap_y = RS == 1 && !f32 ? 2 : f32 && (RS == 2 || NS > 0) ? 5 : 8;
+  static constexpr int x = kOcc[v] < cap_x ? kOcc[v] : cap_x;
+  static constexpr int y = kOcc[4 + v] < cap_y ? kOcc[4 + v] : cap_y;
 };
 
-template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS>
-__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
@@ -226,6 +229,8 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Ba
       T un = rowp[P + src];
       T ut = rowp[2 * P + src];
       T e = rowp[3 * P + src];
+      T sx = T(0);  // rho X of the passive scalar (NS)
+      if constexpr (NS > 0) sx = rowp[4 * P + src];
       if (flip) un = -un;
 
       // COMPUTE: primitive variables, slopes, half-step face states
@@ -240,6 +245,16 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Ba
       dq.p = limit<LIM>(q.p - ql.p, qr.p - q.p);
       Prim<T> qm, qp;
       trace(q, ir, dq, lam, G, qm, qp);
+      // passive scalar X = rho X / rho: limited slope, half-step faces with
+      // the advective source -u dX
+      T xm = T(0), xp = T(0);
+      if constexpr (NS > 0) {
+        const T X = sx * ir;
+        const T dX = limit<LIM>(X - from_left(X), from_right(X) - X);
+        const T hs = T(-0.5) * lam * q.u * dX;
+        xm = X - T(0.5) * dX + hs;
+        xp = X + T(0.5) * dX + hs;
+      }
 
       // Riemann problem at this lane's right interface i+1/2
       const Prim<T> qm_next = from_right(qm);
@@ -247,10 +262,17 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Ba
       if (GUESS)
         p_learned = learned_guess<T>(ex.mlp, qp, qm_next, ex.gamma, ex.gate_kappa, ex.gate_theta2);
       int iters;
-      bool conv, fb;
+      bool conv, fb, left;
       T pstar;
-      const Flux<T> F = riemann_flux<RS>(qp, qm_next, G, p_learned, iters, conv, fb, pstar);
+      const Flux<T> F = riemann_flux<RS>(qp, qm_next, G, p_learned, iters, conv, fb, pstar, left);
       const Flux<T> Fl = from_left(F);  // interface i-1/2
+      // scalar flux: mass flux times X on the side of the contact at x/t = 0
+      T FX = T(0), FXl = T(0);
+      if constexpr (NS > 0) {
+        const T xm_next = from_right(xm);
+        FX = F.m * (left ? xp : xm_next);
+        FXl = from_left(FX);
+      }
 
       if (INSTR) {
         // interfaces owned by this segment: x0-1/2 (first segment only) and
@@ -274,6 +296,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::x)) void k_sweep_x(Ba
         outp[P + i] = nn;
         outp[2 * P + i] = nt;
         outp[3 * P + i] = ne;
+        if constexpr (NS > 0) outp[4 * P + i] = sx + lam * (FXl - FX);
         status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
         if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
       }
@@ -302,8 +325,8 @@ __device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, co
   return d;
 }
 
-template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS>
-__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
@@ -333,6 +356,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Ba
       if (flip) c.n = -c.n;
       return c;
     };
+    auto load_scalar = [&](int j) {  // rho X (NS): copied at walls
+      bool flip;
+      return col[4 * P + (long long)ghost_source(j, d.ny, d.bc, flip) * d.pitch];
+    };
 
     // One loop body does everything: iteration j READs cell j+2, traces cell
     // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
@@ -346,6 +373,9 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Ba
     Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
     T smax = T(0);  // max of T values is exact; widened once for the atomic
     int status = 0;
+    // passive scalar (NS): rho X and X of the window, faces, fluxes
+    T s0 = T(0), s1 = T(0), s2 = T(0), X0 = T(0), X1 = T(0), X2 = T(0);
+    T xm1 = T(0), xp1 = T(0), xp0 = T(0), FX = T(0), FmX = T(0);
 #pragma unroll 3
     for (int j = y0 - 4; j < y1; ++j) {
       c0 = c1;
@@ -355,15 +385,32 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Ba
       ir1 = ir2;
       c2 = load(j + 2);
       q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
-      if (j >= y0 - 2) trace(q1, ir1, slopes<LIM>(q0, q1, q2), lam, G, qm1, qp1);
+      if constexpr (NS > 0) {
+        s0 = s1;
+        s1 = s2;
+        X0 = X1;
+        X1 = X2;
+        s2 = load_scalar(j + 2);
+        X2 = s2 * ir2;
+      }
+      if (j >= y0 - 2) {
+        trace(q1, ir1, slopes<LIM>(q0, q1, q2), lam, G, qm1, qp1);
+        if constexpr (NS > 0) {
+          const T dX = limit<LIM>(X1 - X0, X2 - X1);
+          const T hs = T(-0.5) * lam * q1.u * dX;
+          xm1 = X1 - T(0.5) * dX + hs;
+          xp1 = X1 + T(0.5) * dX + hs;
+        }
+      }
       if (j >= y0 - 1) {
         T p_learned = T(0);
         if (GUESS)
           p_learned = learned_guess<T>(ex.mlp, qp0, qm1, ex.gamma, ex.gate_kappa, ex.gate_theta2);
         int iters;
-        bool conv, fb;
+        bool conv, fb, left;
         T pstar;
-        F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar);
+        F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar, left);
+        if constexpr (NS > 0) FX = F.m * (left ? xp0 : xm1);
         if (INSTR) {
           const bool valid = xin && (j >= y0 || y0 == 0);
           count_newton(st, valid, conv ? iters : 0);
@@ -387,12 +434,18 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS>::y)) void k_sweep_y(Ba
           __builtin_nontemporal_store(nt, out + P + off);
           __builtin_nontemporal_store(nn, out + 2 * P + off);
           __builtin_nontemporal_store(ne, out + 3 * P + off);
+          if constexpr (NS > 0)
+            __builtin_nontemporal_store(s0 + lam * (FmX - FX), out + 4 * P + off);
           status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
           if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
         }
       }
       qp0 = qp1;
       Fm = F;
+      if constexpr (NS > 0) {
+        xp0 = xp1;
+        FmX = FX;
+      }
     }
     if (status) atomicOr(&st->status, status);
     if constexpr (FUSE) {
@@ -430,7 +483,8 @@ __global__ __launch_bounds__(256) void k_copy(Batch<T> b) {
     const long long base = d.off + (w - d.r0) * d.pitch;
     for (int x = lane; x < d.nx; x += kWave) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b.dst[base + v * d.plane + x] = b.src[base + v * d.plane + x];
+      for (int v = 0; v < kMaxVars; ++v)
+        if (v < b.nv) b.dst[base + v * d.plane + x] = b.src[base + v * d.plane + x];
     }
   }
 }
@@ -483,7 +537,7 @@ __global__ void k_clear_stats(DevState* st, int n) {
 // partials in a fixed order.  Results do not depend on scheduling.
 template <typename T>
 __global__ __launch_bounds__(256) void k_totals(Batch<T> b, double* partials) {
-  __shared__ double sh[4][256];
+  __shared__ double sh[kMaxVars][256];
   int lo = 0, hi = b.ngrids - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -494,47 +548,49 @@ __global__ __launch_bounds__(256) void k_totals(Batch<T> b, double* partials) {
   }
   const GridDesc d = b.g[lo];
   const int k = blockIdx.x - d.tb0;
-  double s[4] = {0, 0, 0, 0};
+  double s[kMaxVars] = {};
   for (int y = k; y < d.ny; y += d.ntb) {
     const T* rowp = b.src + d.off + (long long)y * d.pitch;
     for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) s[v] += (double)rowp[v * d.plane + x];
+      for (int v = 0; v < kMaxVars; ++v)
+        if (v < b.nv) s[v] += (double)rowp[v * d.plane + x];
     }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
+  for (int v = 0; v < kMaxVars; ++v) sh[v][threadIdx.x] = s[v];
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+      for (int v = 0; v < kMaxVars; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
     }
     __syncthreads();
   }
-  if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < kMaxVars) partials[blockIdx.x * kMaxVars + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(256) void k_totals_final(const GridDesc* g, const double* partials,
                                                       DevState* st) {
-  __shared__ double sh[4][256];
+  __shared__ double sh[kMaxVars][256];
   const GridDesc d = g[blockIdx.x];
-  double s[4] = {0, 0, 0, 0};
+  double s[kMaxVars] = {};
   for (int k = threadIdx.x; k < d.ntb; k += blockDim.x) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) s[v] += partials[(d.tb0 + k) * 4 + v];
+    for (int v = 0; v < kMaxVars; ++v) s[v] += partials[(d.tb0 + k) * kMaxVars + v];
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
+  for (int v = 0; v < kMaxVars; ++v) sh[v][threadIdx.x] = s[v];
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+      for (int v = 0; v < kMaxVars; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
     }
     __syncthreads();
   }
-  if (threadIdx.x < 4) st[blockIdx.x].totals[threadIdx.x] = sh[threadIdx.x][0] * (d.h * d.h);
+  if (threadIdx.x < kMaxVars)
+    st[blockIdx.x].totals[threadIdx.x] = sh[threadIdx.x][0] * (d.h * d.h);
 }
 
 // ------------------------------------------------------------ launchers
@@ -545,12 +601,13 @@ static inline unsigned blocks_for(long long items, unsigned max_blocks) {
 }
 
 // Sweep kernel variants: instrumentation, learned guess, fused reduction,
-// limiter and interface solver are template arguments; index = instr +
-// 2 guess + 4 fuse + 8 limiter + 24 solver.  The HLLC flux iterates nothing,
-// so it has neither instrumented nor learned-guess variants (null entries).
+// limiter, interface solver and passive scalars are template arguments;
+// index = instr + 2 guess + 4 fuse + 8 limiter + 24 solver + 72 scalars.  The
+// HLLC flux iterates nothing, so it has neither instrumented nor
+// learned-guess variants (null entries).
 template <typename T>
 using SweepFn = void (*)(Batch<T>, Gas<T>, Extras);
-constexpr int kSweepVariants = 2 * 2 * 2 * 3 * 3;
+constexpr int kSweepVariants = 2 * 2 * 2 * 3 * 3 * (kMaxScalars + 1);
 
 template <typename T, int DIR, int V>
 constexpr SweepFn<T> sweep_variant() {
@@ -558,13 +615,14 @@ constexpr SweepFn<T> sweep_variant() {
   constexpr int GS = (V >> 1) & 1;
   constexpr bool F = (V >> 2) & 1;
   constexpr int L = (V >> 3) % 3;
-  constexpr int RS = V / 24;
+  constexpr int RS = (V / 24) % 3;
+  constexpr int NS = V / 72;
   if constexpr (RS == 2 && (I || GS))
     return nullptr;
   else if constexpr (DIR == 0)
-    return &k_sweep_x<T, I, GS, L, F, RS>;
+    return &k_sweep_x<T, I, GS, L, F, RS, NS>;
   else
-    return &k_sweep_y<T, I, GS, L, F, RS>;
+    return &k_sweep_y<T, I, GS, L, F, RS, NS>;
 }
 
 template <typename T, int DIR, int... V>
@@ -573,20 +631,24 @@ SweepFn<T> sweep_table(int v, std::integer_sequence<int, V...>) {
   return table[v];
 }
 
-// The variant for the options; null for an invalid limiter or solver.  With
-// the HLLC flux the instrumentation and the learned guess do not apply.
+// The variant for the options; null for an invalid limiter, solver or
+// scalar count.  With the HLLC flux the instrumentation and the learned guess
+// do not apply.
 template <typename T, int DIR>
-SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter, int riemann) {
-  if (limiter < 0 || limiter > 2 || riemann < 0 || riemann > 2) return nullptr;
+SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter, int riemann, int ns) {
+  if (limiter < 0 || limiter > 2 || riemann < 0 || riemann > 2 || ns < 0 || ns > kMaxScalars)
+    return nullptr;
   if (riemann == 2) instr = false, guess = 0;
-  const int v = (instr ? 1 : 0) + (guess ? 2 : 0) + (fuse ? 4 : 0) + 8 * limiter + 24 * riemann;
+  const int v = (instr ? 1 : 0) + (guess ? 2 : 0) + (fuse ? 4 : 0) + 8 * limiter + 24 * riemann +
+                72 * ns;
   return sweep_table<T, DIR>(v, std::make_integer_sequence<int, kSweepVariants>());
 }
 
 template <typename T>
 hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  const SweepFn<T> k = sweep_kernel<T, 0>(instr, guess, ex.fuse != 0, G.limiter, G.riemann);
+  const SweepFn<T> k =
+      sweep_kernel<T, 0>(instr, guess, ex.fuse != 0, G.limiter, G.riemann, b.nv - 4);
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
                      s, b, G, ex);
@@ -594,8 +656,8 @@ hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
 }
 
 template <typename T>
-int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int riemann) {
-  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, fuse, limiter, riemann);
+int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int riemann, int ns) {
+  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, fuse, limiter, riemann, ns);
   if (!k) return 0;
   int nb = 0;
   const hipError_t e =
@@ -606,7 +668,8 @@ int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int rie
 template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s) {
-  const SweepFn<T> k = sweep_kernel<T, 1>(instr, guess, ex.fuse != 0, G.limiter, G.riemann);
+  const SweepFn<T> k =
+      sweep_kernel<T, 1>(instr, guess, ex.fuse != 0, G.limiter, G.riemann, b.nv - 4);
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
                      s, b, G, ex);
@@ -662,7 +725,7 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
                                         int, unsigned, hipStream_t);                          \
   template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
                                         int, unsigned, hipStream_t);                          \
-  template int sweep_y_blocks_per_cu<T>(bool, int, bool, int, int);                           \
+  template int sweep_y_blocks_per_cu<T>(bool, int, bool, int, int, int);                      \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \
   template hipError_t launch_totals<T>(const Batch<T>&, int, double*, hipStream_t);

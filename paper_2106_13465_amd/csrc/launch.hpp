@@ -12,9 +12,9 @@ namespace hydro {
 // instr: Newton statistics and (if ex.log) the interface logger; guess: 1 =
 // learned starting guess from ex.mlp.  With ex.fuse the sweep folds the max
 // wave speed of its output into st[].acc (the last sweep of a step).  These,
-// G.limiter and G.riemann pick a compiled variant of the kernel (a limiter or
-// solver outside 0..2 returns hipErrorInvalidValue); with the HLLC flux
-// instr and guess are ignored.
+// G.limiter, G.riemann and the passive scalars (b.nv - 4) pick a compiled
+// variant of the kernel (values outside the built ones return
+// hipErrorInvalidValue); with the HLLC flux instr and guess are ignored.
 template <typename T>
 hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s);
@@ -24,7 +24,7 @@ hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
 // Resident blocks per CU of the y-sweep variant (runtime occupancy query),
 // for sizing its work items to whole rounds of the chip; 0 on error.
 template <typename T>
-int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int riemann);
+int sweep_y_blocks_per_cu(bool instr, int guess, bool fuse, int limiter, int riemann, int ns);
 template <typename T>
 hipError_t launch_max_speed(const Batch<T>& b, const Gas<T>& G, hipStream_t s);
 template <typename T>

@@ -60,6 +60,7 @@ Batch<T> batch_of(const Plan& p, const void* src, void* dst, int seg, long long 
   b.st = p.st;
   b.ngrids = p.n;
   b.seg = seg;
+  b.nv = 4 + p.nscalars;
   b.items = items;
   return b;
 }
@@ -169,7 +170,7 @@ hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_
   }
   HIP_TRY(hipMalloc((void**)&st, sizeof(DevState) * n));
   HIP_TRY(hipMalloc((void**)&d_desc, sizeof(GridDesc) * n));
-  HIP_TRY(hipMalloc((void**)&partials, sizeof(double) * 4 * tot_blocks));
+  HIP_TRY(hipMalloc((void**)&partials, sizeof(double) * kMaxVars * tot_blocks));
   HIP_TRY(hipMalloc((void**)&log_count, sizeof(unsigned long long)));
   HIP_TRY(hipMemset(log_count, 0, sizeof(unsigned long long)));
   HIP_TRY(hipMemset(st, 0, sizeof(DevState) * n));
@@ -202,7 +203,8 @@ hipError_t Plan::bind(void* U_, const long* pitches, const long long* offsets, i
   pitch.assign(pitches, pitches + n);
   off.assign(offsets, offsets + n);
   long long total = 0;
-  for (int g = 0; g < n; ++g) total = std::max(total, off[g] + 4LL * pitch[g] * ny[g]);
+  const long long nv = 4 + nscalars;
+  for (int g = 0; g < n; ++g) total = std::max(total, off[g] + nv * pitch[g] * ny[g]);
   dtype = dtype_;
   const size_t bytes = elem_size() * (size_t)total;
   if (v_bytes != bytes) {
@@ -396,9 +398,9 @@ hipError_t Plan::sync_states(std::vector<DevState>& out) {
 namespace {
 
 std::mutex g_tune_mu;
-// keyed by dtype, kernel variant (starting guess, limiter, solver) and grid
-// shapes
-using TuneKey = std::tuple<int, int, int, int, std::vector<int>>;
+// keyed by dtype, kernel variant (starting guess, limiter, solver, passive
+// scalars) and grid shapes
+using TuneKey = std::tuple<int, int, int, int, int, std::vector<int>>;
 std::map<TuneKey, LaunchCfg> g_tune_cache;
 
 TuneKey tune_key(const Plan& p) {
@@ -410,7 +412,7 @@ TuneKey tune_key(const Plan& p) {
     shape.push_back(p.bc[g]);
   }
   const int guess = (p.opt.guess == HYDRO_GUESS_MLP && p.mlp) ? 1 : 0;
-  return {p.dtype, guess, p.opt.limiter, p.opt.riemann, shape};
+  return {p.dtype, guess, p.opt.limiter, p.opt.riemann, p.nscalars, shape};
 }
 
 }  // namespace
@@ -494,9 +496,9 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
       const int guess = (opt.guess == HYDRO_GUESS_MLP && mlp) ? 1 : 0;
       const int bpc = dtype == HYDRO_F64
                           ? sweep_y_blocks_per_cu<double>(instr, guess, true, opt.limiter,
-                                                          opt.riemann)
+                                                          opt.riemann, nscalars)
                           : sweep_y_blocks_per_cu<float>(instr, guess, true, opt.limiter,
-                                                         opt.riemann);
+                                                         opt.riemann, nscalars);
       const long long slots = (long long)cus * bpc * kWavesPerBlock;
       auto items_for = [&](int sy) {
         long long it = 0;

@@ -29,6 +29,7 @@ struct Plan {
   std::vector<long long> off;
   long long elems = 0;  // elements per state buffer
   double gamma = 1.4, cfl = 0.8;
+  int nscalars = 0;     // passive scalars: the state has 4 + nscalars planes
   // options and launch shape
   hydro_options_t opt{};
   LaunchCfg cfg;

@@ -34,15 +34,16 @@ def _padded_pitch(nx: int, dtype: torch.dtype) -> int:
 class Hydro:
     """One grid: ``Hydro(nx, ny, gamma, cfl, bc, dtype)``.
 
-    The state lives in ``self.U`` (a torch tensor [4, ny, pitch] on the current
-    HIP device; planes rho, rho u, rho v, E); ``self.state`` is its [4, ny, nx]
-    view.  Work runs on a stream of the handle's own (a new torch stream at the
+    The state lives in ``self.U`` (a torch tensor [4 + nscalars, ny, pitch] on
+    the current HIP device; planes rho, rho u, rho v, E, then rho X for each
+    passive scalar X); ``self.state`` is its [4 + nscalars, ny, nx] view.  Work runs on a stream of the handle's own (a new torch stream at the
     default priority unless one is given), so the step can be graph-captured.
     """
 
     def __init__(self, nx: int, ny: int, gamma: float = 1.4, cfl: float = 0.8,
                  bc="periodic", dtype: torch.dtype = torch.float64, device="cuda",
-                 pitch: int | None = None, stream: torch.cuda.Stream | None = None):
+                 pitch: int | None = None, stream: torch.cuda.Stream | None = None,
+                 nscalars: int = 0):
         self.lib = _lib.load()
         if dtype not in _DTYPE:
             raise ValueError(f"dtype {dtype}: float64 or float32")
@@ -56,8 +57,10 @@ class Hydro:
             self.handle = self.lib.hydro_create(self.nx, self.ny, self.gamma, self.cfl, self.bc)
             if not self.handle:
                 raise HydroError(_lib.HYDRO_EINVAL, _lib.last_error())
+            check(self.lib.hydro_set_scalars(self.handle, int(nscalars)))
+            self.nv = 4 + int(nscalars)
             self.pitch = int(pitch) if pitch is not None else _padded_pitch(self.nx, dtype)
-            self.U = torch.zeros((4, self.ny, self.pitch), dtype=dtype, device=self.device)
+            self.U = torch.zeros((self.nv, self.ny, self.pitch), dtype=dtype, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             self._bind()
 
@@ -87,10 +90,11 @@ class Hydro:
         return 1.0 / max(self.nx, self.ny)
 
     def set_state(self, U) -> None:
-        """Copy a [4, ny, nx] array (numpy or torch) into the bound state."""
+        """Copy a [4 + nscalars, ny, nx] array (numpy or torch) into the bound
+        state."""
         t = torch.as_tensor(np.asarray(U) if not isinstance(U, torch.Tensor) else U)
-        if tuple(t.shape) != (4, self.ny, self.nx):
-            raise ValueError(f"state shape {tuple(t.shape)} != (4, {self.ny}, {self.nx})")
+        if tuple(t.shape) != (self.nv, self.ny, self.nx):
+            raise ValueError(f"state shape {tuple(t.shape)} != ({self.nv}, {self.ny}, {self.nx})")
         self.stream.synchronize()
         torch.cuda.synchronize(self.device)
         self.state.copy_(t.to(device=self.device, dtype=self.dtype))
@@ -134,7 +138,7 @@ class Hydro:
             check(self.lib.hydro_step(self.handle))
 
     def totals(self) -> np.ndarray:
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * self.nv)()
         check(self.lib.hydro_conserved_totals(self.handle, out))
         return np.array(list(out))
 
@@ -213,12 +217,13 @@ class HydroBatch:
 
     ``shapes`` is a list of (nx, ny); ``bc`` one boundary type or one per grid.
     The packed state lives in ``self.buf`` (1D torch tensor, layout of
-    hydro_batch_layout); ``self.view(g)`` is grid g's [4, ny, nx] view.
+    hydro_batch_layout); ``self.view(g)`` is grid g's [4 + nscalars, ny, nx]
+    view.
     """
 
     def __init__(self, shapes, gamma: float = 1.4, cfl: float = 0.8, bc="reflect",
                  dtype: torch.dtype = torch.float32, device="cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, nscalars: int = 0):
         self.lib = _lib.load()
         if dtype not in _DTYPE:
             raise ValueError(f"dtype {dtype}: float64 or float32")
@@ -237,6 +242,8 @@ class HydroBatch:
             self.handle = self.lib.hydro_batch_create(self.n, nx, ny, float(gamma), float(cfl), bcc)
             if not self.handle:
                 raise HydroError(_lib.HYDRO_EINVAL, _lib.last_error())
+            check(self.lib.hydro_batch_set_scalars(self.handle, int(nscalars)))
+            self.nv = 4 + int(nscalars)
             offs = (ctypes.c_longlong * self.n)()
             pitches = (ctypes.c_long * self.n)()
             total = self.lib.hydro_batch_layout(self.handle, _DTYPE[dtype], offs, pitches)
@@ -265,7 +272,7 @@ class HydroBatch:
         nx, ny = self.shapes[g]
         p = self.pitches[g]
         o = self.offsets[g]
-        return self.buf[o: o + 4 * ny * p].view(4, ny, p)[:, :, :nx]
+        return self.buf[o: o + self.nv * ny * p].view(self.nv, ny, p)[:, :, :nx]
 
     def set_states(self, states) -> None:
         self.stream.synchronize()
@@ -273,8 +280,8 @@ class HydroBatch:
         for g, U in enumerate(states):
             t = torch.as_tensor(np.asarray(U) if not isinstance(U, torch.Tensor) else U)
             nx, ny = self.shapes[g]
-            if tuple(t.shape) != (4, ny, nx):
-                raise ValueError(f"grid {g}: shape {tuple(t.shape)} != (4, {ny}, {nx})")
+            if tuple(t.shape) != (self.nv, ny, nx):
+                raise ValueError(f"grid {g}: shape {tuple(t.shape)} != ({self.nv}, {ny}, {nx})")
             self.view(g).copy_(t.to(device=self.device, dtype=self.dtype))
         torch.cuda.synchronize(self.device)
         check(self.lib.hydro_batch_invalidate(self.handle))
@@ -308,9 +315,9 @@ class HydroBatch:
         check(self.lib.hydro_batch_graph_steps(self.handle, int(nsteps)))
 
     def totals(self) -> np.ndarray:
-        out = (ctypes.c_double * (4 * self.n))()
+        out = (ctypes.c_double * (self.nv * self.n))()
         check(self.lib.hydro_batch_totals(self.handle, out))
-        return np.array(list(out)).reshape(self.n, 4)
+        return np.array(list(out)).reshape(self.n, self.nv)
 
     def clock(self):
         t = (ctypes.c_double * self.n)()

@@ -238,3 +238,138 @@ def test_solver_option_validation(torch_cuda):
     with pytest.raises(HydroError):
         h.set_options(riemann=2, guess=1)
     assert h.options()["riemann"] == 0
+
+
+# ------------------------------------------------------------------ passive scalars
+def with_scalar(U, seed):
+    _, ny, nx = U.shape
+    return inputs.with_scalars(U, inputs.random_scalars(nx, ny, seed=seed))
+
+
+def make_s(torch_cuda, V, bc, dtype=None, **opts):
+    from paper_2106_13465_amd.hydro import Hydro
+
+    dtype = dtype or torch_cuda.float64
+    _, ny, nx = V.shape
+    h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, nscalars=V.shape[0] - 4)
+    if opts:
+        h.set_options(**opts)
+    h.set_state(V)
+    return h
+
+
+@pytest.mark.parametrize("bc", [1, 2, 3])
+@pytest.mark.parametrize("riemann", [0, 1, 2])
+def test_scalar_steps_fp64(torch_cuda, orc, riemann, bc):
+    V = with_scalar(inputs.random_states(110, 70, seed=400 + bc, rough=0.6), 10 + riemann)
+    h = make_s(torch_cuda, V, bc, riemann=riemann)
+    h.step(5)
+    ref = V.copy()
+    c = orc.cfg(bc=bc, riemann=riemann, nscalars=1)
+    for _ in range(5):
+        orc.step(ref, c)
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("riemann", [0, 2])
+def test_scalar_single_sweeps_fp64(torch_cuda, orc, riemann):
+    V = with_scalar(inputs.random_states(97, 66, seed=410, rough=0.9), 11)
+    for direction in (0, 1):
+        h = make_s(torch_cuda, V, 1, riemann=riemann)
+        dt = h.compute_dt()
+        h.sweep(direction)
+        ref = V.copy()
+        orc.sweep(ref, direction, dt, orc.cfg(bc=1, riemann=riemann, nscalars=1))
+        assert rel_err(h.get_state(), ref) <= TOL64, direction
+
+
+def test_scalar_uniform_follows_density(torch_cuda):
+    U = inputs.random_states(90, 60, seed=411, rough=0.7)
+    V = inputs.with_scalars(U, np.full((60, 90), 0.5))
+    h = make_s(torch_cuda, V, 1, limiter=1, order=1)
+    h.step(6)
+    S = h.get_state()
+    np.testing.assert_allclose(S[4], 0.5 * S[0], rtol=1e-14, atol=0)
+
+
+def test_scalar_with_options_graph_and_stats(torch_cuda, orc):
+    """MC limiter, alternating order and statistics with a scalar, through
+    graph replays (bitwise equal to eager steps) and against the oracle."""
+    V = with_scalar(inputs.random_states(96, 72, seed=412, rough=0.6), 12)
+    a = make_s(torch_cuda, V, 3, limiter=1, order=1, stats=1)
+    b = make_s(torch_cuda, V, 3, limiter=1, order=1)
+    a.step(4)
+    b.graph_steps(1)
+    b.graph_steps(3)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    ref = V.copy()
+    hist = np.zeros(11, dtype=np.int64)
+    c = orc.cfg(bc=3, limiter=1, order=1, nscalars=1)
+    for s in range(4):
+        orc.step(ref, c, hist, step_index=s)
+    assert rel_err(a.get_state(), ref) <= TOL64
+    g = np.array(a.stats()["hist"][:11])
+    assert g.sum() == hist.sum() and np.abs(g - hist).sum() <= 0.01 * hist.sum()
+
+
+def test_scalar_totals(torch_cuda, orc):
+    V = with_scalar(inputs.random_states(80, 50, seed=413, rough=0.6), 13)
+    h = make_s(torch_cuda, V, 3)
+    T0 = h.totals()
+    assert len(T0) == 5
+    np.testing.assert_allclose(T0, orc.totals(V), rtol=1e-14, atol=1e-16)
+    h.step(5)
+    T1 = h.totals()
+    assert abs(T1[4] - T0[4]) <= 1e-13 * np.abs(V[4]).mean()
+
+
+@pytest.mark.parametrize("riemann", [0, 2])
+def test_scalar_fp32_l1(torch_cuda, orc, riemann):
+    U = inputs.random_smooth(150, 110, seed=414, amp=0.5)
+    X = 2.0 + np.sin(np.linspace(0.0, 6.0, 150))[None, :] * np.cos(np.linspace(0.0, 4.0, 110))[:, None]
+    V = inputs.with_scalars(U, X)
+    h = make_s(torch_cuda, V, 3, dtype=torch_cuda.float32, riemann=riemann)
+    h.step(10)
+    ref = V.copy()
+    c = orc.cfg(bc=3, riemann=riemann, nscalars=1)
+    for _ in range(10):
+        orc.step(ref, c)
+    got = h.get_state().astype(np.float64)
+    for k in range(5):
+        assert np.abs(got[k] - ref[k]).sum() / np.abs(ref[k]).sum() < 1e-5, k
+
+
+def test_scalar_batch(torch_cuda, orc):
+    from paper_2106_13465_amd.hydro import HydroBatch
+
+    shapes = [(70, 33), (45, 91), (128, 64)]
+    bcs = [3, 1, 2]
+    states = [with_scalar(inputs.random_states(nx, ny, seed=420 + g, rough=0.6), 20 + g)
+              for g, (nx, ny) in enumerate(shapes)]
+    b = HydroBatch(shapes, 1.4, 0.8, bcs, dtype=torch_cuda.float64, nscalars=1)
+    b.set_options(riemann=1)
+    b.set_states(states)
+    b.graph_steps(2)
+    b.step(1)
+    got = b.get_states()
+    tot = b.totals()
+    assert tot.shape == (3, 5)
+    for g, V in enumerate(states):
+        ref = V.copy()
+        c = orc.cfg(bc=bcs[g], riemann=1, nscalars=1)
+        for _ in range(3):
+            orc.step(ref, c)
+        assert rel_err(got[g], ref) <= TOL64, g
+        np.testing.assert_allclose(tot[g], orc.totals(ref), rtol=1e-12, atol=1e-14)
+
+
+def test_scalar_count_checks(torch_cuda):
+    from paper_2106_13465_amd import _lib
+    from paper_2106_13465_amd.hydro import Hydro, HydroError
+
+    with pytest.raises(HydroError):
+        Hydro(16, 16, 1.4, 0.8, "periodic", nscalars=2)
+    h = Hydro(16, 16, 1.4, 0.8, "periodic", nscalars=1)
+    assert h.lib.hydro_set_scalars(h.handle, 0) == _lib.HYDRO_ESTATE
+    with pytest.raises(ValueError):
+        h.set_state(np.ones((4, 16, 16)))
