@@ -67,13 +67,14 @@ SOLVERS = {"two_shock": 0, "exact": 1, "hllc": 2}
 
 def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True, limiter=0,
             order=0, riemann=0):
+    """U has 4 + n planes for n passive scalars."""
     import torch
 
     from paper_2106_13465_amd.hydro import Hydro
 
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     _, ny, nx = U.shape
-    h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0")
+    h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0", nscalars=U.shape[0] - 4)
     h.set_options(limiter=limiter, order=order, riemann=riemann)
     if seg_x or seg_y:
         h.set_options(seg_x=seg_x, seg_y=seg_y)
@@ -114,9 +115,9 @@ def newton_report(h):
             "hist": {str(k): n for k, n in enumerate(hist) if n}}
 
 
-def sweep_record(cells, elem, phase):
+def sweep_record(cells, elem, phase, nv=4):
     ms = phase["ms"] / max(phase["launches"], 1)
-    alg_bytes = cells * 8 * elem  # read 4 words + write 4 words per cell
+    alg_bytes = cells * 2 * nv * elem  # read nv words + write nv words per cell
     gbs = alg_bytes / (ms * 1e-3) / 1e9
     return {"avg_ms": ms, "launches": phase["launches"], "cell_updates_per_s": cells / (ms * 1e-3),
             "algorithmic_bytes": alg_bytes, "hbm_gbps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
@@ -144,7 +145,8 @@ def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
 
     bc = {"periodic": oracle.BC_PERIODIC, "reflect": oracle.BC_REFLECT,
           "outflow": oracle.BC_OUTFLOW}[bc_name]
-    c = oracle.cfg(bc=bc, limiter=limiter, order=order, riemann=riemann)
+    c = oracle.cfg(bc=bc, limiter=limiter, order=order, riemann=riemann,
+                   nscalars=U.shape[0] - 4)
     V = U.copy()
     _, ny, nx = V.shape
     t0 = time.perf_counter()
@@ -536,6 +538,8 @@ def main() -> int:
                     help="sweep order: x then y every step, or alternating xy / yx")
     ap.add_argument("--riemann", choices=sorted(SOLVERS), default="two_shock",
                     help="interface solver")
+    ap.add_argument("--scalars", type=int, choices=[0, 1], default=0,
+                    help="passive scalars carried (a smooth seeded field)")
     ap.add_argument("--seg-x", type=int, default=0)
     ap.add_argument("--seg-y", type=int, default=0)
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -571,6 +575,12 @@ def main() -> int:
     U, bc, desc = workload(args.workload, args.size)
     _, ny, nx = U.shape
     cells = nx * ny
+    if args.scalars:
+        from paper_2106_13465_amd import inputs
+
+        U = inputs.with_scalars(U, inputs.random_scalars(nx, ny, seed=7, k=args.scalars))
+        desc += f"; {args.scalars} passive scalar (seeded smooth field plus noise)"
+    nv = U.shape[0]
 
     variants = [args.dtype] + ([] if args.no_f32 or args.dtype == "f32" else ["f32"])
     results = {}
@@ -583,8 +593,8 @@ def main() -> int:
                        SOLVERS[args.riemann])
         elem = 8 if dn == "f64" else 4
         ms_step = r["ms_total"] / args.steps
-        sx = sweep_record(cells, elem, r["profile"]["sweep_x"])
-        sy = sweep_record(cells, elem, r["profile"]["sweep_y"])
+        sx = sweep_record(cells, elem, r["profile"]["sweep_x"], nv)
+        sy = sweep_record(cells, elem, r["profile"]["sweep_y"], nv)
         results[dn] = {
             "value": 2.0 * cells * args.steps / (r["ms_total"] * 1e-3),
             "ms_per_step": ms_step,
@@ -611,7 +621,8 @@ def main() -> int:
     sx, sy = res["sweeps"]["x"], res["sweeps"]["y"]
     dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
     # the counter summaries are taken with the default limiter, order and solver
-    default_opts = args.limiter == "minmod" and args.order == "xy" and args.riemann == "two_shock"
+    default_opts = (args.limiter == "minmod" and args.order == "xy" and args.riemann == "two_shock"
+                    and args.scalars == 0)
     traffic = pmc_traffic(args.workload, dom_name, main_dn) if default_opts else None
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
@@ -633,7 +644,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": desc, "nx": nx, "ny": ny, "bc": bc, "gamma": 1.4, "cfl": 0.8,
                    "limiter": args.limiter, "sweep_order": args.order,
-                   "riemann": args.riemann,
+                   "riemann": args.riemann, "passive_scalars": args.scalars,
                    "newton_cap": 10, "newton_tol": 1e-8,
                    "parallelism": "single GPU"},
         "sweeps": res["sweeps"],
@@ -644,7 +655,7 @@ def main() -> int:
     if "f32" in results and main_dn != "f32":
         r32 = results["f32"]
         a, b = states["f32"].astype(np.float64), states[main_dn]
-        l1 = [float(np.abs(a[k] - b[k]).sum() / max(np.abs(b[k]).sum(), 1e-300)) for k in range(4)]
+        l1 = [float(np.abs(a[k] - b[k]).sum() / max(np.abs(b[k]).sum(), 1e-300)) for k in range(nv)]
         line["f32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                        "sweeps": r32["sweeps"], "newton": r32["newton"],
                        "speedup_vs_f64": r32["value"] / res["value"],
