@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PMC_SUMMARY = {"fourier_blasts": "sweep_fourier_blasts_8192_pmc.json",
                "multiblast_batch": "sweep_multiblast_batch_256_pmc.json",
                "quadrant_batch": "sweep_quadrant_batch_64_pmc.json"}
-KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/godunov.hpp",
+KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd/csrc/sweeps.hpp",
+                  "paper_2106_13465_amd/csrc/godunov.hpp",
                   "paper_2106_13465_amd/csrc/fastmath.hpp", "paper_2106_13465_amd/csrc/device_state.hpp",
                   "paper_2106_13465_amd/csrc/mlp.hpp"]
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhydro.so")
 # (source, floating-point contraction)
 SOURCES = [("api.cpp", "off"), ("plan.cpp", "off"), ("kernels.hip", "fast"),
-           ("mlp_kernels.hip", "fast")]
+           ("kernels_scalar.hip", "fast"), ("mlp_kernels.hip", "fast")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -52,14 +53,18 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel, at most 4 at a time) and link."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src, contract in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        _run([HIPCC, *FLAGS, f"-ffp-contract={contract}", "-fno-gpu-rdc",
-              "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([HIPCC, *FLAGS, f"-ffp-contract={contract}", "-fno-gpu-rdc",
+                      "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
