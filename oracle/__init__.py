@@ -105,6 +105,7 @@ def _load():
             [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg), ctypes.c_long, _LL]),
         "oracle_totals": (None, [_D, ctypes.c_int, ctypes.c_int, _D]),
         "oracle_threads": (ctypes.c_int, []),
+        "oracle_set_threads": (None, [ctypes.c_int]),
         "mlp_oracle_nparams": (ctypes.c_int, []),
         "mlp_oracle_bf16": (ctypes.c_double, [ctypes.c_double]),
         "mlp_oracle_forward": (ctypes.c_double, [_D, _D, ctypes.c_int, _D]),
@@ -301,6 +302,11 @@ def totals(U: np.ndarray) -> np.ndarray:
 
 def threads() -> int:
     return _load().oracle_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the sweeps (results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- learned-guess network

@@ -182,6 +182,8 @@ void oracle_totals_n(const double *U, int nx, int ny, int nvars, double *out);
 
 /* number of OpenMP threads the sweeps use (1 when built without OpenMP) */
 int oracle_threads(void);
+/* set that number (n > 0); results do not depend on it */
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }
