@@ -51,6 +51,10 @@ def workload(name: str, n: int):
         return inputs.fourier_blasts(n), "periodic", (
             f"fourier_blasts {n}x{n}: rho = 1 + 0.3 S, u, v in [-0.5, 0.5] from 16 seeded "
             "Fourier modes (k <= 8), p = 1, 8 seeded point blasts E = 1/h^2; periodic")
+    if name == "fourier_smooth":
+        return inputs.fourier_blasts(n, nblasts=0), "periodic", (
+            f"fourier_smooth {n}x{n}: the fourier_blasts field without the blasts (the "
+            "flow moves: dt ~ 1e-4 instead of 2e-8); periodic")
     if name == "shear_layer":
         return inputs.shear_layer(n), "periodic", (
             f"shear_layer {n}x{n}: Kelvin-Helmholtz layer rho 2/1, u +-0.5, p 2.5, "
@@ -540,11 +544,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=0,
-                    help="grid side (default: 8192 fourier_blasts, 4096 shear_layer, "
+                    help="grid side (default: 8192 fourier_blasts and fourier_smooth, 4096 shear_layer, "
                          "128 blast_corner)")
     ap.add_argument("--workload", default="fourier_blasts",
-                    choices=["fourier_blasts", "shear_layer", "blast_corner", "multiblast_batch",
-                             "quadrant_batch", "learned"])
+                    choices=["fourier_blasts", "fourier_smooth", "shear_layer", "blast_corner",
+                             "multiblast_batch", "quadrant_batch", "learned"])
     ap.add_argument("--train-records", type=int, default=10_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
@@ -588,7 +592,8 @@ def main() -> int:
         return 0
 
     if not args.size:
-        args.size = {"fourier_blasts": 8192, "shear_layer": 4096, "blast_corner": 128}.get(
+        args.size = {"fourier_blasts": 8192, "fourier_smooth": 8192, "shear_layer": 4096,
+                     "blast_corner": 128}.get(
             args.workload, 8192)
     print(f"# generating {args.workload} {args.size}^2", file=sys.stderr, flush=True)
     U, bc, desc = workload(args.workload, args.size)
