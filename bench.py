@@ -173,12 +173,32 @@ def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
         sec1 = time.perf_counter() - t1
     finally:
         oracle.set_threads(threads)
+    # the paper's three OpenMP schemes on the same corner (speedup tables in
+    # the form of its Figures 11-13); each step equals the serial one bitwise
+    names = {oracle.SCHEME_FINE: "fine_grain", oracle.SCHEME_COARSE: "coarse_grain",
+             oracle.SCHEME_TASKS: "tasks"}
+    counts = [t for t in (1, 2, 4, 8, 16) if t <= max(threads, 1)]
+    schemes = {}
+    for sc, name in names.items():
+        rows = []
+        for t in counts:
+            X = W.copy()
+            t2 = time.perf_counter()
+            oracle.step_scheme(X, c, sc, t)
+            rows.append({"threads": t, "seconds": time.perf_counter() - t2})
+        for r in rows:
+            r["speedup"] = rows[0]["seconds"] / r["seconds"]
+            r["efficiency"] = r["speedup"] / r["threads"]
+        schemes[name] = rows
+    oracle.set_threads(threads)
     return {"value": 2.0 * nx * ny / sec, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle", "seconds": sec,
             "sample": f"1 full step (dt, x-sweep, y-sweep) of the same {nx}x{ny} input, FP64, "
                       f"{threads} OpenMP threads over pencils",
             "single_core": {"value": 2.0 * m * m / sec1, "seconds": sec1,
-                            "sample": f"1 step of the top-left {m}x{m} corner, 1 thread"}}
+                            "sample": f"1 step of the top-left {m}x{m} corner, 1 thread"},
+            "openmp_schemes": {"sample": f"1 step of the top-left {m}x{m} corner per entry",
+                               **schemes}}
 
 
 BATCH_WORKLOADS = {

@@ -25,6 +25,7 @@ BC_REFLECT, BC_OUTFLOW, BC_PERIODIC = 1, 2, 3
 LIMITER_MINMOD, LIMITER_MC, LIMITER_VANLEER = 0, 1, 2
 ORDER_XY, ORDER_ALTERNATE = 0, 1
 RIEMANN_TWO_SHOCK, RIEMANN_EXACT, RIEMANN_HLLC = 0, 1, 2
+SCHEME_FINE, SCHEME_COARSE, SCHEME_TASKS = 0, 1, 2
 DIR_X, DIR_Y = 0, 1
 RHO_MIN = 1e-10
 C_MIN = 1e-10
@@ -106,6 +107,11 @@ def _load():
         "oracle_totals": (None, [_D, ctypes.c_int, ctypes.c_int, _D]),
         "oracle_threads": (ctypes.c_int, []),
         "oracle_set_threads": (None, [ctypes.c_int]),
+        "oracle_step_scheme": (ctypes.c_double, [_D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Cfg),
+                                                 ctypes.c_int, ctypes.c_int]),
+        "oracle_scheme_decomposition": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_int)]),
         "mlp_oracle_nparams": (ctypes.c_int, []),
         "mlp_oracle_bf16": (ctypes.c_double, [ctypes.c_double]),
         "mlp_oracle_forward": (ctypes.c_double, [_D, _D, ctypes.c_int, _D]),
@@ -302,6 +308,22 @@ def totals(U: np.ndarray) -> np.ndarray:
 
 def threads() -> int:
     return _load().oracle_threads()
+
+
+def step_scheme(U: np.ndarray, c: Cfg, scheme: int, threads: int) -> float:
+    """One time step parallelised by one of the paper's OpenMP schemes
+    (SCHEME_FINE, SCHEME_COARSE, SCHEME_TASKS) on `threads` threads; the
+    result equals step(U, c) bitwise.  Returns dt."""
+    _grid(U, c)
+    _, ny, nx = U.shape
+    return _load().oracle_step_scheme(_dptr(U), nx, ny, ctypes.byref(c), int(scheme), int(threads))
+
+
+def scheme_decomposition(threads: int, nx: int, ny: int):
+    px, py = ctypes.c_int(), ctypes.c_int()
+    _load().oracle_scheme_decomposition(int(threads), int(nx), int(ny), ctypes.byref(px),
+                                        ctypes.byref(py))
+    return px.value, py.value
 
 
 def set_threads(n: int) -> None:

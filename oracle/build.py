@@ -1,8 +1,8 @@
 """Compile the C oracle (test infrastructure) into oracle/liboracle.so with gcc.
 
 Flags: -O2 -ffp-contract=off so that every floating-point operation rounds once,
-in source order, and -fopenmp for the pencil-parallel loop of the sweeps (its
-result does not depend on the thread count).
+in source order, and -fopenmp for the pencil-parallel loop of the sweeps and the
+paper's other OpenMP schemes (their results do not depend on the thread count).
 """
 from __future__ import annotations
 
@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["hydro_oracle.c", "mlp_oracle.c"]
+SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "openmp_schemes.c"]
 OUT = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
           "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]

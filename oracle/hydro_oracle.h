@@ -180,6 +180,19 @@ void oracle_totals(const double *U, int nx, int ny, double out[4]);
 /* the same for nvars planes (4 + passive scalars) */
 void oracle_totals_n(const double *U, int nx, int ny, int nvars, double *out);
 
+/* The paper's OpenMP parallelisations of a time step (openmp_schemes.c):
+ * the pencil-parallel loop (fine grain), one subdomain per thread with a
+ * neighbour busy-wait barrier (coarse grain), and subdomain tasks with
+ * interface-buffer dependencies (tasks).  Each gives oracle_step bitwise.
+ * Returns dt. */
+#define ORACLE_SCHEME_FINE 0
+#define ORACLE_SCHEME_COARSE 1
+#define ORACLE_SCHEME_TASKS 2
+double oracle_step_scheme(double *U, int nx, int ny, const oracle_cfg *c, int scheme,
+                          int threads);
+/* the px x py decomposition the coarse-grain and task schemes use */
+void oracle_scheme_decomposition(int threads, int nx, int ny, int *px, int *py);
+
 /* number of OpenMP threads the sweeps use (1 when built without OpenMP) */
 int oracle_threads(void);
 /* set that number (n > 0); results do not depend on it */
