@@ -145,6 +145,31 @@ def pmc_traffic(workload_name: str, kernel: str, dtype_name: str):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+VALU_SUMMARY = {"fourier_blasts": "sweep_fourier_blasts_8192_valu.json"}
+
+
+def valu_issue(workload_name: str, kernel: str, dtype_name: str, measured_ms: float):
+    """The competing bound beside HBM: the committed instruction-count summary
+    gives the sweep's VALU instructions per launch; at 4 cycles per wave64
+    instruction on 1024 SIMDs at 2.4 GHz they need `issue_floor_ms`.  frac =
+    floor / the launch time measured now.  None if missing or taken from
+    different kernel sources."""
+    if workload_name not in VALU_SUMMARY:
+        return None
+    try:
+        with open(os.path.join(ROOT, "profiles", VALU_SUMMARY[workload_name])) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}_{dtype_name}")
+    if ent is None:
+        return None
+    return {"valu_per_lane_cell": ent["valu_per_lane_cell"], "issue_floor_ms": ent["issue_floor_ms"],
+            "measured_ms": measured_ms, "frac": ent["issue_floor_ms"] / measured_ms}
+
+
 def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
     """The oracle timed on this host: one full step of the whole input on all
     OpenMP threads (the reported value), and one step of its top-left 2048^2
@@ -671,7 +696,9 @@ def main() -> int:
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
                 "traffic": traffic, "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
-                "avg_launch_ms": dom["avg_ms"]}
+                "avg_launch_ms": dom["avg_ms"],
+                "valu_issue": valu_issue(args.workload, dom_name, main_dn, dom["avg_ms"])
+                if default_opts else None}
 
     line = {
         "metric": METRIC,
