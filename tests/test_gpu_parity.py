@@ -19,15 +19,19 @@ TOL64 = 1e-12
 
 
 def var_scales(b):
-    """Scale of each conserved variable of the reference state b [4, ...]."""
+    """Scale of each conserved variable of the reference state b [4 + ns, ...]:
+    max |.| for rho, E and the passive scalars' rho X, the momentum scale
+    max sqrt(2 rho E) (or max |m| if larger) for the momenta."""
     mom = np.max(np.sqrt(2.0 * np.abs(b[0]) * np.abs(b[3])))
     scales = [np.max(np.abs(b[0])), max(mom, np.max(np.abs(b[1]))),
               max(mom, np.max(np.abs(b[2]))), np.max(np.abs(b[3]))]
+    scales += [np.max(np.abs(b[k])) for k in range(4, b.shape[0])]
     return [s if s > 0 else 1.0 for s in scales]
 
 
 def rel_err(a, b):
-    """Per-variable normwise relative error, max over the 4 variables."""
+    """Per-variable normwise relative error, max over every plane."""
+    assert a.shape == b.shape
     return max(np.max(np.abs(a[k] - b[k])) / s for k, s in enumerate(var_scales(b)))
 
 
