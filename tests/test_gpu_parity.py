@@ -173,6 +173,31 @@ def test_fp32_l1(torch_cuda, orc, bc):
         assert l1 < 1e-5
 
 
+@pytest.mark.parametrize("n", [128, 256])
+def test_fp32_error_below_truncation(torch_cuda, orc, n):
+    """Equal accuracy: a density wave rho = 1 + 0.2 sin(2 pi (x + y)) carried
+    by (u, v) = (1, 1) at p = 1 on a periodic grid has the exact solution
+    rho(x - t, y - t).  After 100 steps the FP32 state's L1 distance from the
+    FP64 state is at least ten times below the FP64 scheme's own error
+    against the exact solution (its truncation error)."""
+    h_ = 1.0 / n
+    x = (np.arange(n) + 0.5) * h_
+    X, Y = np.meshgrid(x, x)
+    U = inputs.conservative(1.0 + 0.2 * np.sin(2 * np.pi * (X + Y)), 1.0, 1.0, 1.0)
+    a = make(torch_cuda, U, 3)
+    b = make(torch_cuda, U, 3, dtype=torch_cuda.float32)
+    a.step(100)
+    b.step(100)
+    t, _, _ = a.clock()
+    exact = 1.0 + 0.2 * np.sin(2 * np.pi * (X + Y - 2 * t))
+    r64 = a.get_state()[0]
+    r32 = b.get_state()[0].astype(np.float64)
+    trunc = np.abs(r64 - exact).sum() / np.abs(exact).sum()
+    fp32 = np.abs(r32 - r64).sum() / np.abs(r64).sum()
+    print(f"n={n} t={t:.4f} truncation L1 {trunc:.2e} FP32 L1 {fp32:.2e}")
+    assert fp32 <= 0.1 * trunc
+
+
 def test_graph_replay_matches_eager(torch_cuda, orc):
     """A captured multi-step graph, replayed several times with eager steps and
     host synchronisation in between, matches eager stepping bitwise after
