@@ -116,8 +116,12 @@ def newton_report(h):
     hist = s["hist"]
     conv = sum(hist[1:])
     mean = sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1)
+    wh = s["wave_hist"]
+    waves = sum(wh)
     return {"interfaces": s["interfaces"], "mean_iterations": mean, "unconverged": hist[0],
-            "hist": {str(k): n for k, n in enumerate(hist) if n}}
+            "hist": {str(k): n for k, n in enumerate(hist) if n},
+            "wave_mean_max_iterations": sum(k * n for k, n in enumerate(wh)) / max(waves, 1),
+            "wave_hist": {str(k): n for k, n in enumerate(wh) if n}}
 
 
 def sweep_record(cells, elem, phase, nv=4):
@@ -291,7 +295,9 @@ def bench_batch(args) -> dict:
     hist = st["hist"]
     conv = sum(hist[1:])
     newton = {"interfaces": st["interfaces"], "unconverged": hist[0],
-              "mean_iterations": sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1)}
+              "mean_iterations": sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1),
+              "wave_mean_max_iterations": sum(k * n for k, n in enumerate(st["wave_hist"]))
+              / max(sum(st["wave_hist"]), 1)}
     t, n, _ = b.clock()
     b.close()
     del b
@@ -363,8 +369,10 @@ def _iter_stats(obj):
     s = obj.stats(reset=True)
     hist = s["hist"]
     conv = sum(hist[1:])
+    wh = s["wave_hist"]
     return {"interfaces": s["interfaces"], "unconverged": hist[0], "fallbacks": s["fallbacks"],
             "mean_iterations": sum(k * n for k, n in enumerate(hist) if k > 0) / max(conv, 1),
+            "wave_mean_max_iterations": sum(k * n for k, n in enumerate(wh)) / max(sum(wh), 1),
             "fallback_rate": s["fallbacks"] / max(s["interfaces"], 1)}
 
 

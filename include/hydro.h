@@ -122,6 +122,11 @@ typedef struct {
                                             iterations; hist[0]: iteration
                                             cap reached unconverged         */
   long long fallbacks;                   /* learned guess rejected          */
+  long long wave_hist[HYDRO_MAX_NITER + 1]; /* groups of interfaces a wave
+                                            solves together (up to 64) by
+                                            their largest iteration count
+                                            (the cap for an unconverged one):
+                                            the wave runs that many          */
 } hydro_stats_t;
 
 /* Launch shape chosen by the autotuner (hydro_autotune / hydro_batch_autotune).

@@ -54,6 +54,7 @@ class hydro_stats_t(ctypes.Structure):
         ("interfaces", ctypes.c_longlong),
         ("hist", ctypes.c_longlong * (HYDRO_MAX_NITER + 1)),
         ("fallbacks", ctypes.c_longlong),
+        ("wave_hist", ctypes.c_longlong * (HYDRO_MAX_NITER + 1)),
     ]
 
 

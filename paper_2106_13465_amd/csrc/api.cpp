@@ -229,7 +229,10 @@ int do_stats(hydro::Plan* p, hydro_stats_t* out, int reset) {
     std::memset(out, 0, sizeof *out);
     for (int i = 0; i < p->n; ++i) {
       out->interfaces += (long long)s[i].interfaces;
-      for (int k = 0; k <= HYDRO_MAX_NITER; ++k) out->hist[k] += (long long)s[i].hist[k];
+      for (int k = 0; k <= HYDRO_MAX_NITER; ++k) {
+        out->hist[k] += (long long)s[i].hist[k];
+        out->wave_hist[k] += (long long)s[i].wave_hist[k];
+      }
       out->fallbacks += (long long)s[i].fallbacks;
     }
   }

@@ -38,6 +38,7 @@ struct DevState {
   double totals[kMaxVars];
   unsigned long long interfaces;          // Riemann problems counted
   unsigned long long hist[kMaxIter + 1];  // [0] unconverged, [k] k iterations
+  unsigned long long wave_hist[kMaxIter + 1];  // waves by their largest count
   unsigned long long fallbacks;           // learned guesses rejected
 };
 

@@ -107,7 +107,10 @@ __global__ void k_clear_stats(DevState* st, int n) {
   const int gi = blockIdx.x;
   const int i = threadIdx.x;
   if (gi >= n) return;
-  if (i <= kMaxIter) st[gi].hist[i] = 0ull;
+  if (i <= kMaxIter) {
+    st[gi].hist[i] = 0ull;
+    st[gi].wave_hist[i] = 0ull;
+  }
   if (i == 0) {
     st[gi].interfaces = 0ull;
     st[gi].fallbacks = 0ull;

@@ -59,7 +59,11 @@ __device__ __forceinline__ void fold_max(unsigned long long* acc, double v) {
     atomicMax(acc, bits);
 }
 
-__device__ __forceinline__ void count_newton(DevState* st, bool valid, int key) {
+// Newton statistics of one wave's interfaces (valid lanes): the histogram of
+// key (iterations to convergence, 0 = unconverged) per interface, and of the
+// wave's largest iteration count `iters` (iterations run, the cap for an
+// unconverged interface), which is what the wave's time follows.
+__device__ __forceinline__ void count_newton(DevState* st, bool valid, int key, int iters) {
   const int lane = threadIdx.x & (kWave - 1);
   bool mine = valid;
   unsigned long long all = __ballot(valid);
@@ -74,6 +78,11 @@ __device__ __forceinline__ void count_newton(DevState* st, bool valid, int key) 
     if (lane == leader) atomicAdd(&st->hist[k], (unsigned long long)__popcll(same));
     if (key == k) mine = false;
   }
+  int m = valid ? iters : 0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off));
+  if (all != 0ull && lane == __ffsll((long long)all) - 1)
+    atomicAdd(&st->wave_hist[min(m, kMaxIter)], 1ull);
 }
 
 __device__ __forceinline__ void count_flag(unsigned long long* counter, bool flag) {
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_
         // interfaces owned by this segment: x0-1/2 (first segment only) and
         // the right interfaces of its cells
         const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
-        count_newton(st, valid, conv ? iters : 0);
+        count_newton(st, valid, conv ? iters : 0, iters);
         if (GUESS) count_flag(&st->fallbacks, valid && fb);
         if (ex.log)
           log_interface(ex, valid, qp, qm_next, pstar,
@@ -393,7 +402,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
         if constexpr (NS > 0) FX = F.m * (left ? xp0 : xm1);
         if (INSTR) {
           const bool valid = xin && (j >= y0 || y0 == 0);
-          count_newton(st, valid, conv ? iters : 0);
+          count_newton(st, valid, conv ? iters : 0, iters);
           if (GUESS) count_flag(&st->fallbacks, valid && fb);
           if (ex.log)
             log_interface(ex, valid, qp0, qm1, pstar,

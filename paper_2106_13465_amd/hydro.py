@@ -200,7 +200,8 @@ class Hydro:
 
 
 def _stats_dict(s) -> dict:
-    return {"interfaces": s.interfaces, "hist": list(s.hist), "fallbacks": s.fallbacks}
+    return {"interfaces": s.interfaces, "hist": list(s.hist), "fallbacks": s.fallbacks,
+            "wave_hist": list(s.wave_hist)}
 
 
 def _tune_dict(t) -> dict:

@@ -155,6 +155,14 @@ def test_stats_counts(torch_cuda, orc):
     assert g.sum() == hist.sum()
     # iteration counts may differ where rounding decides a convergence test
     assert np.abs(g - hist).sum() <= 0.01 * hist.sum()
+    # per-wave maxima: one group per x-sweep segment (3 per row of 130 cells)
+    # and per y-sweep interface row of each 64-column group (71 x 3)
+    w = np.array(s["wave_hist"][:11])
+    assert w.sum() == 70 * 3 + 71 * 3
+    assert w[0] == 0
+    top = 10 if g[0] else int(np.nonzero(g)[0].max())
+    assert int(np.nonzero(w)[0].max()) == top
+    assert 64 * (w * np.arange(11)).sum() >= (g * np.arange(11)).sum() + 10 * g[0]
 
 
 @pytest.mark.parametrize("bc", [1, 3])
