@@ -17,7 +17,10 @@
  * star pressure by Newton on the two-shock wave function from the
  * two-rarefaction guess, stopped at |dp| <= tol*p or after niter iterations;
  * linear sampling across rarefaction fans; CFL time step
- * dt = cfl * h / max(|u|+c, |v|+c); floors rho >= 1e-10, c >= 1e-10.
+ * dt = cfl * h / max(|u|+c, |v|+c); floors rho >= 1e-10, c >= 1e-10; x-sweep
+ * then y-sweep every step.  Options (hydro_options_t) select the MC or van
+ * Leer limiter, an alternating sweep order, the exact Riemann solver or the
+ * HLLC flux; hydro_set_scalars adds passive scalars.
  *
  * STATE LAYOUT.  U is a caller-owned device array [4 + ns][ny][pitch] of
  * float64 (HYDRO_F64) or float32 (HYDRO_F32): planes rho, rho*u, rho*v, E,
