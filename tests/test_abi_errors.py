@@ -48,6 +48,10 @@ def test_null_handles(lib):
     assert lib.hydro_conserved_totals(None, out) == _lib.HYDRO_EINVAL
     assert lib.hydro_bind(None, None, 8, 0, None) == _lib.HYDRO_EINVAL
     assert lib.hydro_batch_layout(None, 0, None, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_set_scalars(None, 0) == _lib.HYDRO_EINVAL
+    assert lib.hydro_batch_set_scalars(None, 1) == _lib.HYDRO_EINVAL
+    st = _lib.hydro_stats_t()
+    assert lib.hydro_riemann_stats(None, ctypes.byref(st), 0) == _lib.HYDRO_EINVAL
     lib.hydro_destroy(None)  # no-op
     lib.hydro_batch_destroy(None)
 
