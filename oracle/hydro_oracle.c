@@ -163,8 +163,12 @@ int oracle_riemann(const double qL[4], const double qR[4], double gamma,
     double usL = qL[1] - (p - qL[3]) / WL;
     double usR = qR[1] + (p - qR[3]) / WR;
     double dp = zL * zR / (zL + zR) * (usL - usR);
+    /* on the floor with the step pointing below it: f(p_min) > 0 (f
+     * increasing), the root lies under the floor and the floored star
+     * pressure is the floor itself (reading) */
+    int below_floor = p == pmin && p + dp < pmin;
     p = fmax(p + dp, pmin);
-    if (fabs(dp) <= tol * p) {
+    if (fabs(dp) <= tol * p || below_floor) {
       conv = 1;
       break;
     }
@@ -300,8 +304,9 @@ int oracle_riemann_exact(const double qL[4], const double qR[4], double gamma,
     exact_curve(qL, g, p, &fL, &dfL);
     exact_curve(qR, g, p, &fR, &dfR);
     double dp = -(fL + fR + (qR[1] - qL[1])) / (dfL + dfR);
+    int below_floor = p == pmin && p + dp < pmin; /* as in oracle_riemann */
     p = fmax(p + dp, pmin);
-    if (fabs(dp) <= tol * p) {
+    if (fabs(dp) <= tol * p || below_floor) {
       conv = 1;
       break;
     }

@@ -104,8 +104,10 @@ double oracle_two_shock_f(const double qL[4], const double qR[4], double gamma,
                           double p);
 
 /* Riemann problem at one interface.  Star pressure by Newton on the
- * two-shock function from the two-rarefaction guess, stopped at
- * |dp| <= tol*p or after niter iterations; then the Godunov state at x/t = 0.
+ * two-shock function from the two-rarefaction guess, floored at p_min,
+ * stopped at |dp| <= tol*p, or when an iteration that starts on the floor
+ * points below it (the root lies under the floor, so the star pressure is the
+ * floor), or after niter iterations; then the Godunov state at x/t = 0.
  * Returns the number of iterations done; *converged says whether the test
  * was met.  qg receives (rho, u_n, u_t, p) at the interface; pstar/ustar may
  * be NULL. */

@@ -229,3 +229,29 @@ def test_newton_iteration_cap(orc):
     qR = prim_state(1.0, -50.0, 0.0, 1e-6)
     _, _, _, it, conv = orc.riemann(qL, qR, G, niter=2, tol=1e-14)
     assert it == 2 and not conv
+
+
+def test_floor_is_the_star_pressure_below_it(orc):
+    """When the root of f lies under the pressure floor (near vacuum), the
+    iteration that starts on the floor points below it and stops there: the
+    star pressure is the floor, reached at once when the guess is already
+    the floor (vacuum generation makes the two-rarefaction numerator
+    non-positive) and when the exact root is positive but tiny."""
+    pmin = orc.p_floor(1.0, G)
+    # receding faster than the vacuum threshold 2 (cL + cR)/(gamma - 1)
+    qL, qR = prim_state(1.0, -7.0, 0.0, 1.0), prim_state(1.0, 7.0, 0.0, 1.0)
+    for solve in (orc.riemann, orc.riemann_exact):
+        _, p, us, it, conv = solve(qL, qR, G)
+        assert conv and it == 1 and p == pmin and us == 0.0
+    # just under the threshold with p a little above the floor: the exact
+    # root (two rarefactions, so the guess formula gives it) is ~1e-40
+    c = math.sqrt(G * 1e-19)
+    du = 0.999 * 4.0 * c / (G - 1.0)
+    qL, qR = prim_state(1.0, -du / 2, 0.0, 1e-19), prim_state(1.0, du / 2, 0.0, 1e-19)
+    for solve in (orc.riemann, orc.riemann_exact):
+        _, p, _, it, conv = solve(qL, qR, G)
+        assert conv and it == 1 and p == pmin
+    # a root above the floor is not affected: convergence by the step test
+    qL, qR = prim_state(1.0, -0.5, 0.0, 1.0), prim_state(0.5, 0.5, 0.0, 0.8)
+    _, p, _, it, conv = orc.riemann(qL, qR, G)
+    assert conv and p > 100 * pmin
