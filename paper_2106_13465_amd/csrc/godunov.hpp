@@ -293,8 +293,11 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
       exact_curve(pp, ip, R.r, R.p, cR, izR, G, fR, dR, yR);
       dp = -(fL + fR + (R.u - L.u)) * fm::rcp(dL + dR);
     }
+    // a step from the floor that points below it: the root lies under the
+    // floor (f increasing), so the floored star pressure is the floor
+    const bool below_floor = pp == pmin && pp + dp < pmin;
     pp = fmax(pp + dp, pmin);
-    return fabs(dp) <= G.tol * pp;
+    return fabs(dp) <= G.tol * pp || below_floor;
   };
   // The first iteration runs for every interface as straight-line code; the
   // loop only carries the interfaces that need more (or fall back).
