@@ -433,9 +433,27 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
   }
   if (!cached) {
     constexpr int kMaxReps = 9;
-    hipEvent_t ev[kMaxReps + 1];
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     const LaunchCfg saved = cfg;
+    // On any error below: the events are destroyed, the launch shape the
+    // handle had is restored with its descriptors, and the max speed is
+    // marked stale (the timed sweeps fold into it).
+    struct Cleanup {
+      Plan* p;
+      LaunchCfg saved;
+      hipEvent_t ev[kMaxReps + 1] = {};
+      bool done = false;
+      ~Cleanup() {
+        for (auto e : ev)
+          if (e) (void)hipEventDestroy(e);
+        if (!done) {
+          p->cfg = saved;
+          p->acc_valid = false;
+          (void)p->upload_descriptors();
+        }
+      }
+    } guard{this, saved};
+    hipEvent_t* ev = guard.ev;
+    for (int i = 0; i <= kMaxReps; ++i) HIP_TRY(hipEventCreate(&ev[i]));
     // sweeps read U and write V only; dt must be set for the kernels to run
     HIP_TRY(enqueue_max_speed());
     HIP_TRY(enqueue_finalize(false, false));
@@ -547,7 +565,7 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     best.blocks_x = wx.blocks_x;
     best.seg_y = wy.seg_y;
     best.blocks_y = wy.blocks_y;
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    guard.done = true;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
