@@ -64,10 +64,12 @@ __device__ __forceinline__ Prim<T> cons_to_prim(T U0, T Un, T Ut, T E, const Gas
   return q;
 }
 
-// minmod: the argument of smaller magnitude if both have the same sign, else 0
+// minmod: the argument of smaller magnitude if both have the same sign, else 0,
+// as max(min(a, b), min(0, max(a, b))): both positive gives the smaller, both
+// negative the larger (smaller magnitude), opposite signs or a zero give 0
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
-  return a * b > T(0) ? copysign(fmin(fabs(a), fabs(b)), a) : T(0);
+  return fmax(fmin(a, b), fmin(T(0), fmax(a, b)));
 }
 
 // Limited slope from the two one-sided differences: LIM 0 minmod, 1 MC,
@@ -241,6 +243,8 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   const T cR = fm::sqrt(G.g * R.p * irR);
   const T CL = G.g * L.p * L.r;  // Lagrangian sound speed squared
   const T CR = G.g * R.p * R.r;
+  const T aL = G.half_gm1 * L.p;  // two-shock wave speeds: W_K^2 = rho_K (a_K + (gamma+1)/2 p)
+  const T aR = G.half_gm1 * R.p;
   const T pmin = fmin(L.r, R.r) * G.pfloor;
 
   // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), evaluated as
@@ -275,10 +279,10 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     T dp;
     if constexpr (RS == 0) {
       // two-shock f(p) = sum_K (p - p_K)/W_K + u_R - u_L with
-      // W_K^2 = C_K (1 + gs (p - p_K)/p_K); f' = 1/z_L + 1/z_R,
-      // 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
-      const T XL = CL * (T(1) + G.gs * (pp - L.p) * ipL);
-      const T XR = CR * (T(1) + G.gs * (pp - R.p) * ipR);
+      // W_K^2 = C_K (1 + gs (p - p_K)/p_K) = rho_K ((gamma-1)/2 p_K + (gamma+1)/2 p);
+      // f' = 1/z_L + 1/z_R, 1/z_K = (W_K^2 + C_K) / (2 W_K^3).
+      const T XL = L.r * fma(G.half_gp1, pp, aL);
+      const T XR = R.r * fma(G.half_gp1, pp, aR);
       const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
       const T izL2 = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
       const T izR2 = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
@@ -327,8 +331,8 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   T gr, gu, gp, to;
   if constexpr (RS == 0) {
     // star velocity (average of the two sides' estimates) at the final p
-    const T XL = CL * (T(1) + G.gs * (p - L.p) * ipL);
-    const T XR = CR * (T(1) + G.gs * (p - R.p) * ipR);
+    const T XL = L.r * fma(G.half_gp1, p, aL);
+    const T XR = R.r * fma(G.half_gp1, p, aR);
     const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
     const T usL = L.u - (p - L.p) * iWL;
     const T usR = R.u + (p - R.p) * iWR;
