@@ -30,8 +30,9 @@
  * Interior cells only: ghost cells never live in user memory.  Cells are
  * square, h = 1 / max(nx, ny).  The library never frees caller memory.
  * Sweeps are out of place: the handle owns a second buffer of the same size
- * (allocated by hydro_bind), an x-sweep writes it and the y-sweep writes U
- * back, so after every call U holds the current state.
+ * (allocated by hydro_bind); the first sweep of a step writes it, the second
+ * writes U back, and a lone hydro_sweep copies its result back, so after
+ * every call U holds the current state.
  *
  * ERRORS.  Every call returns HYDRO_OK (0) or a negative code and sets a
  * thread-local message (hydro_last_error).  No call aborts or throws.
@@ -172,8 +173,8 @@ int hydro_set_scalars(hydro_t *h, int n);
  * after modifying U outside the library. */
 int hydro_bind(hydro_t *h, void *U, long pitch, int dtype, void *hip_stream);
 
-/* Forget the max wave speed fused into the last y-sweep (U changed outside
- * the library). */
+/* Forget the max wave speed fused into the last step's second sweep (U
+ * changed outside the library). */
 int hydro_invalidate(hydro_t *h);
 
 int hydro_set_options(hydro_t *h, const hydro_options_t *o);
@@ -191,9 +192,10 @@ double hydro_compute_dt(hydro_t *h);
 int hydro_sweep(hydro_t *h, int dir);
 
 /* One time step: dt from the current state (taken from the max wave speed
- * fused into the previous step's y-sweep when still valid, otherwise from a
- * reduction over U), x-sweep, y-sweep; t += dt, step += 1 on the device.
- * Asynchronous, no host synchronisation. */
+ * fused into the previous step's second sweep when still valid, otherwise
+ * from a reduction over U), then the x-sweep and the y-sweep (with
+ * HYDRO_ORDER_ALTERNATE: the y-sweep first on odd steps), both with that dt;
+ * t += dt, step += 1 on the device.  Asynchronous, no host synchronisation. */
 int hydro_step(hydro_t *h);
 
 /* out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E, then the
