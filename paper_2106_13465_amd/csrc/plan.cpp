@@ -48,6 +48,12 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   // 2/(gamma - 1) (5 for gamma = 1.4): the exact solver's fan density power
   const double r = std::nearbyint(2.0 / (g - 1.0));
   G.ipow_r = (r >= 1.0 && r <= 64.0 && std::fabs(2.0 / (g - 1.0) - r) <= 1e-12 * r) ? (int)r : 0;
+  // (1 + e)^a = 1 + a e + a(a-1)/2 e^2 + a(a-1)(a-2)/6 e^3 + ..., a = -z
+  double c = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    c *= (-z - k) / (k + 1);
+    G.ser[k] = T(c);
+  }
   return G;
 }
 

@@ -253,7 +253,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_
       int iters;
       bool conv, fb, left;
       T pstar;
-      const Flux<T> F = riemann_flux<RS>(qp, qm_next, G, p_learned, iters, conv, fb, pstar, left);
+      // FP64: the series form of the guess's power in smooth waves (measured
+      // 4% faster on the x-sweep; no gain in FP32 or in the y-sweep's loop)
+      const Flux<T> F = riemann_flux<RS, T, sizeof(T) == 8>(qp, qm_next, G, p_learned, iters,
+                                                            conv, fb, pstar, left);
       const Flux<T> Fl = from_left(F);  // interface i-1/2
       // scalar flux: mass flux times X on the side of the contact at x/t = 0
       T FX = T(0), FXl = T(0);
