@@ -165,6 +165,29 @@ def test_stats_counts(torch_cuda, orc):
     assert 64 * (w * np.arange(11)).sum() >= (g * np.arange(11)).sum() + 10 * g[0]
 
 
+@pytest.mark.parametrize("amp", [1e-3, 3e-2])
+def test_smooth_guess_iterations_and_parity(torch_cuda, orc, amp):
+    """Smooth fields, FP64: at amplitude 1e-3 every x-sweep wave has its
+    face-pressure ratios within 2^-10 of 1, where the kernel takes the
+    two-rarefaction guess's power from its binomial series; at 3e-2 waves of
+    both kinds occur.  The guess must be as good as the oracle's: the same
+    iteration histogram (a wrong series term would cost a second iteration
+    almost everywhere) and the state to the FP64 bar."""
+    U = inputs.random_smooth(190, 70, seed=24, amp=amp)
+    print(f"smooth amp={amp}", flush=True)
+    h = make(torch_cuda, U, 3, stats=1)
+    c = orc.cfg(bc=3)
+    hist = np.zeros(11, dtype=np.int64)
+    ref = U.copy()
+    for _ in range(3):
+        orc.step(ref, c, hist)
+    h.step(3)
+    g = np.array(h.stats()["hist"][:11])
+    assert g.sum() == hist.sum()
+    assert np.abs(g - hist).sum() <= 0.001 * hist.sum()
+    assert rel_err(h.get_state(), ref) <= TOL64
+
+
 @pytest.mark.parametrize("bc", [1, 3])
 def test_fp32_l1(torch_cuda, orc, bc):
     U = inputs.random_smooth(160, 120, seed=43, amp=0.5)
