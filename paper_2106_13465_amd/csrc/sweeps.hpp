@@ -353,90 +353,164 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
       return col[4 * P + (long long)ghost_source(j, d.ny, d.bc, flip) * d.pitch];
     };
 
-    // One loop body does everything: iteration j READs cell j+2, traces cell
-    // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
-    // four iterations only fill the window (uniform guards), so every step of
-    // the method exists at one code location and an interface shared by two
-    // segments is computed bitwise identically by both.
-    Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
-    Prim<T> q0, q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
-    T ir1, ir2 = T(1);
-    Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
-    Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
     T smax = T(0);  // max of T values is exact; widened once for the atomic
     int status = 0;
-    // passive scalar (NS): rho X and X of the window, faces, fluxes
-    T s0 = T(0), s1 = T(0), s2 = T(0), X0 = T(0), X1 = T(0), X2 = T(0);
-    T xm1 = T(0), xp1 = T(0), xp0 = T(0), FX = T(0), FmX = T(0);
+    if constexpr (sizeof(T) == 8 && NS == 0 && LIM == 0 && RS == 0) {
+      // FP64, minmod, two-shock solver, no passive scalar: the loop below
+      // software-pipelined by one row.  Iteration j issues the READ of row
+      // j+3, solves the Riemann problem at j+1/2 from faces traced in the
+      // previous iteration and WRITEs row j while that load is in flight,
+      // then converts row j+3 and traces row j+2, so the load's latency hides
+      // behind the wave's own Riemann solve.  The loop is unrolled by 3 and
+      // runs from a row index that is a multiple of 3 for a multiple of 3
+      // iterations, so every row is converted, traced and solved by the same
+      // unrolled copy whatever the segment bounds: results do not depend on
+      // the launch shape.  (The FP32 sweep and the FP64 MC and HLLC variants
+      // spill with the longer window and keep the loop below.)
+      Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
+      Prim<T> q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
+      T ir2 = T(1);
+      Prim<T> qpA = q1, qmB = q1, qpB = q1;  // qp(j), qm(j+1), qp(j+1)
+      Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
+      const int jb = y0 - 5;                   // first iteration the stencil needs
+      const int j0 = jb - (((jb % 3) + 3) % 3);  // ... moved down to a multiple of 3
+      const int j1 = j0 + (y1 - j0 + 2) / 3 * 3;  // >= y1, a multiple of 3 iterations
 #pragma unroll 3
-    for (int j = y0 - 4; j < y1; ++j) {
-      c0 = c1;
-      c1 = c2;
-      q0 = q1;
-      q1 = q2;
-      ir1 = ir2;
-      c2 = load(j + 2);
-      q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
-      if constexpr (NS > 0) {
-        s0 = s1;
-        s1 = s2;
-        X0 = X1;
-        X1 = X2;
-        s2 = load_scalar(j + 2);
-        X2 = s2 * ir2;
+      for (int j = j0; j < j1; ++j) {
+        // rows outside -2 .. ny+1 are never used (the clamp keeps reads in range)
+        const Cell<T> cn = load(max(min(j + 3, d.ny + 1), -2));
+        if (j >= y0 - 1 && j < y1) {
+          T p_learned = T(0);
+          if (GUESS)
+            p_learned = learned_guess<T>(ex.mlp, qpA, qmB, ex.gamma, ex.gate_kappa, ex.gate_theta2);
+          int iters;
+          bool conv, fb, left;
+          T pstar;
+          F = riemann_flux<RS>(qpA, qmB, G, p_learned, iters, conv, fb, pstar, left);
+          if (INSTR) {
+            const bool valid = xin && (j >= y0 || y0 == 0);
+            count_newton(st, valid, conv ? iters : 0, iters);
+            if (GUESS) count_flag(&st->fallbacks, valid && fb);
+            if (ex.log)
+              log_interface(ex, valid, qpA, qmB, pstar,
+                            ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+                                (((unsigned long long)x * (d.ny + 1) + (j + 1)) * 2ull + 1ull));
+          }
+        }
+        if (j >= y0 && j < y1) {
+          const T nr = c0.r + lam * (Fm.m - F.m);
+          const T nn = c0.n + lam * (Fm.n - F.n);
+          const T nt = c0.t + lam * (Fm.t - F.t);
+          const T ne = c0.e + lam * (Fm.e - F.e);
+          if (xin) {
+            const long long off = (long long)j * d.pitch;
+            __builtin_nontemporal_store(nr, out + off);
+            __builtin_nontemporal_store(nt, out + P + off);
+            __builtin_nontemporal_store(nn, out + 2 * P + off);
+            __builtin_nontemporal_store(ne, out + 3 * P + off);
+            status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+            if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+          }
+        }
+        Fm = F;
+        c0 = c1;
+        c1 = c2;
+        c2 = cn;
+        T ir3;
+        const Prim<T> q3 = cons_to_prim(cn.r, cn.n, cn.t, cn.e, G, ir3);
+        Prim<T> qm2, qp2;
+        trace(q2, ir2, slopes<LIM>(q1, q2, q3), lam, G, qm2, qp2);
+        qpA = qpB;
+        qmB = qm2;
+        qpB = qp2;
+        q1 = q2;
+        q2 = q3;
+        ir2 = ir3;
       }
-      if (j >= y0 - 2) {
-        trace(q1, ir1, slopes<LIM>(q0, q1, q2), lam, G, qm1, qp1);
+    } else {
+      // One loop body does everything: iteration j READs cell j+2, traces cell
+      // j+1, solves the Riemann problem at j+1/2 and WRITEs cell j.  The first
+      // four iterations only fill the window (uniform guards), so every step of
+      // the method exists at one code location and an interface shared by two
+      // segments is computed bitwise identically by both.
+      Cell<T> c0, c1 = {T(1), T(0), T(0), T(1)}, c2 = c1;
+      Prim<T> q0, q1 = {T(1), T(0), T(0), T(1)}, q2 = q1;
+      T ir1, ir2 = T(1);
+      Prim<T> qp0 = q1, qm1 = q1, qp1 = q1;
+      Flux<T> Fm = {T(0), T(0), T(0), T(0)}, F = Fm;
+      // passive scalar (NS): rho X and X of the window, faces, fluxes
+      T s0 = T(0), s1 = T(0), s2 = T(0), X0 = T(0), X1 = T(0), X2 = T(0);
+      T xm1 = T(0), xp1 = T(0), xp0 = T(0), FX = T(0), FmX = T(0);
+#pragma unroll 3
+      for (int j = y0 - 4; j < y1; ++j) {
+        c0 = c1;
+        c1 = c2;
+        q0 = q1;
+        q1 = q2;
+        ir1 = ir2;
+        c2 = load(j + 2);
+        q2 = cons_to_prim(c2.r, c2.n, c2.t, c2.e, G, ir2);
         if constexpr (NS > 0) {
-          const T dX = limit<LIM>(X1 - X0, X2 - X1);
-          const T hs = T(-0.5) * lam * q1.u * dX;
-          xm1 = X1 - T(0.5) * dX + hs;
-          xp1 = X1 + T(0.5) * dX + hs;
+          s0 = s1;
+          s1 = s2;
+          X0 = X1;
+          X1 = X2;
+          s2 = load_scalar(j + 2);
+          X2 = s2 * ir2;
         }
-      }
-      if (j >= y0 - 1) {
-        T p_learned = T(0);
-        if (GUESS)
-          p_learned = learned_guess<T>(ex.mlp, qp0, qm1, ex.gamma, ex.gate_kappa, ex.gate_theta2);
-        int iters;
-        bool conv, fb, left;
-        T pstar;
-        F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar, left);
-        if constexpr (NS > 0) FX = F.m * (left ? xp0 : xm1);
-        if (INSTR) {
-          const bool valid = xin && (j >= y0 || y0 == 0);
-          count_newton(st, valid, conv ? iters : 0, iters);
-          if (GUESS) count_flag(&st->fallbacks, valid && fb);
-          if (ex.log)
-            log_interface(ex, valid, qp0, qm1, pstar,
-                          ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
-                              (((unsigned long long)x * (d.ny + 1) + (j + 1)) * 2ull + 1ull));
+        if (j >= y0 - 2) {
+          trace(q1, ir1, slopes<LIM>(q0, q1, q2), lam, G, qm1, qp1);
+          if constexpr (NS > 0) {
+            const T dX = limit<LIM>(X1 - X0, X2 - X1);
+            const T hs = T(-0.5) * lam * q1.u * dX;
+            xm1 = X1 - T(0.5) * dX + hs;
+            xp1 = X1 + T(0.5) * dX + hs;
+          }
         }
-      }
-      if (j >= y0) {
-        const T nr = c0.r + lam * (Fm.m - F.m);
-        const T nn = c0.n + lam * (Fm.n - F.n);
-        const T nt = c0.t + lam * (Fm.t - F.t);
-        const T ne = c0.e + lam * (Fm.e - F.e);
-        if (xin) {
-          const long long off = (long long)j * d.pitch;
-          // streaming stores: the next sweep reads these only after the
-          // whole grid (measured faster for the y-sweep, slower for the x-sweep)
-          __builtin_nontemporal_store(nr, out + off);
-          __builtin_nontemporal_store(nt, out + P + off);
-          __builtin_nontemporal_store(nn, out + 2 * P + off);
-          __builtin_nontemporal_store(ne, out + 3 * P + off);
-          if constexpr (NS > 0)
-            __builtin_nontemporal_store(s0 + lam * (FmX - FX), out + 4 * P + off);
-          status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-          if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+        if (j >= y0 - 1) {
+          T p_learned = T(0);
+          if (GUESS)
+            p_learned = learned_guess<T>(ex.mlp, qp0, qm1, ex.gamma, ex.gate_kappa, ex.gate_theta2);
+          int iters;
+          bool conv, fb, left;
+          T pstar;
+          F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar, left);
+          if constexpr (NS > 0) FX = F.m * (left ? xp0 : xm1);
+          if (INSTR) {
+            const bool valid = xin && (j >= y0 || y0 == 0);
+            count_newton(st, valid, conv ? iters : 0, iters);
+            if (GUESS) count_flag(&st->fallbacks, valid && fb);
+            if (ex.log)
+              log_interface(ex, valid, qp0, qm1, pstar,
+                            ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+                                (((unsigned long long)x * (d.ny + 1) + (j + 1)) * 2ull + 1ull));
+          }
         }
-      }
-      qp0 = qp1;
-      Fm = F;
-      if constexpr (NS > 0) {
-        xp0 = xp1;
-        FmX = FX;
+        if (j >= y0) {
+          const T nr = c0.r + lam * (Fm.m - F.m);
+          const T nn = c0.n + lam * (Fm.n - F.n);
+          const T nt = c0.t + lam * (Fm.t - F.t);
+          const T ne = c0.e + lam * (Fm.e - F.e);
+          if (xin) {
+            const long long off = (long long)j * d.pitch;
+            // streaming stores: the next sweep reads these only after the
+            // whole grid (measured faster for the y-sweep, slower for the x-sweep)
+            __builtin_nontemporal_store(nr, out + off);
+            __builtin_nontemporal_store(nt, out + P + off);
+            __builtin_nontemporal_store(nn, out + 2 * P + off);
+            __builtin_nontemporal_store(ne, out + 3 * P + off);
+            if constexpr (NS > 0)
+              __builtin_nontemporal_store(s0 + lam * (FmX - FX), out + 4 * P + off);
+            status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
+            if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+          }
+        }
+        qp0 = qp1;
+        Fm = F;
+        if constexpr (NS > 0) {
+          xp0 = xp1;
+          FmX = FX;
+        }
       }
     }
     if (status) atomicOr(&st->status, status);
