@@ -65,6 +65,71 @@ def test_trace_linear_advection(orc):
     assert math.isclose(qp[2], 0.1 + 0.15 - 0.5 * lam * u * 0.3, rel_tol=1e-15)
 
 
+def _cons(q, gamma):
+    """Conservative variables of a primitive state (rho, u_n, u_t, p); complex safe."""
+    r, u, t, p = q
+    return np.array([r, r * u, r * t, p / (gamma - 1.0) + 0.5 * r * (u * u + t * t)])
+
+
+def _euler_flux(q, gamma):
+    """Conservative Euler flux normal to x of a primitive state; complex safe."""
+    r, u, t, p = q
+    E = p / (gamma - 1.0) + 0.5 * r * (u * u + t * t)
+    return np.array([r * u, r * u * u + p, r * u * t, u * (E + p)])
+
+
+def _primitive_rate(q, dq, gamma):
+    """dq/dt of the 1D Euler equations for the linear profile q + x dq (x in
+    cells) at x = 0, derived from the conservative form U_t = -F(U)_x alone:
+    F_x by a complex step along dq, then q_t = (dU/dq)^-1 U_t with the Jacobian
+    of the ideal-gas conservative variables, also by complex steps (exact to
+    rounding for these polynomial maps)."""
+    eps = 1e-30
+    q = np.asarray(q, dtype=np.complex128)
+    Ft = -np.imag(_euler_flux(q + 1j * eps * np.asarray(dq), gamma)) / eps
+    J = np.empty((4, 4))
+    for k in range(4):
+        e = np.zeros(4, dtype=np.complex128)
+        e[k] = 1j * eps
+        J[:, k] = np.imag(_cons(q + e, gamma)) / eps
+    return np.linalg.solve(J, Ft)
+
+
+def test_trace_source_from_conservative_form(orc):
+    """The half-step source of the trace, S = -A(q) dq, equals the primitive
+    time derivative that the conservative Euler equations give for a linear
+    profile: every term of A (continuity, momentum, energy in pressure form) is
+    checked without retyping it.  The face pair keeps the full slope
+    (qp - qm = dq) and shares the half-step shift (qp + qm)/2 - q = (dt/h) S / 2."""
+    rng = np.random.Generator(np.random.PCG64(54))
+    for _ in range(300):
+        rho, p = np.exp(rng.uniform(-2, 2, size=2))
+        u, ut = rng.uniform(-2, 2, size=2)
+        q = np.array([rho, u, ut, p])
+        dq = rng.uniform(-0.05, 0.05, size=4) * np.array([rho, 1.0, 1.0, p])
+        lam = rng.uniform(0.05, 0.5)
+        qm, qp = orc.trace(q, dq, G, lam)
+        S = _primitive_rate(q, dq, G)
+        shift = 0.5 * (qp + qm) - q
+        scale = np.abs(q) + np.abs(dq) + 1.0
+        np.testing.assert_allclose(shift, 0.5 * lam * S, rtol=0, atol=1e-14 * scale.max())
+        np.testing.assert_allclose(qp - qm, dq, rtol=0, atol=1e-14 * scale.max())
+
+
+def test_trace_velocity_slope_compresses_density(orc):
+    """A velocity slope alone (dq = (0, du, 0, 0)): the density faces keep no
+    jump and both move by the compression -rho du, times half the step, as the
+    continuity equation rho_t = -(rho u)_x fixes for uniform density; the
+    pressure faces move by -gamma p du (adiabatic compression)."""
+    rho, u, p, du, lam = 1.7, 0.3, 2.2, 0.08, 0.45
+    qm, qp = orc.trace([rho, u, -0.4, p], [0.0, du, 0.0, 0.0], G, lam)
+    assert qp[0] - qm[0] == 0.0
+    assert math.isclose(qp[0] - rho, -0.5 * lam * rho * du, rel_tol=1e-13)
+    assert math.isclose(qm[0] - rho, -0.5 * lam * rho * du, rel_tol=1e-13)
+    assert math.isclose(0.5 * (qp[3] + qm[3]) - p, -0.5 * lam * G * p * du, rel_tol=1e-13)
+    assert math.isclose(qp[1] - qm[1], du, rel_tol=1e-14)
+
+
 # ------------------------------------------------------------------ star pressure
 def _random_pair(rng, kind):
     """Random left/right states whose exact solution has the wave pattern
