@@ -75,15 +75,19 @@ def test_fullsize_step(torch_cuda_fs, orc, state, dtype_name, riemann, ns):
         assert abs(dt_gpu - dt_or) <= 1e-13 * dt_or
     G = h.get_state()
     h.close()
-    from test_gpu_parity import var_scales
+    from test_gpu_parity import momentum_err_away_from_blasts, var_scales
 
     for x in sample_columns(U):
         ref = oracle_column_after_step(orc, U, x, dt_or, c)
         got = G[:, :, x].astype(np.float64)
         scales = var_scales(ref)
+        if dtype_name == "f64":
+            away = momentum_err_away_from_blasts(got, ref)
+            print(f"column {x} momentum away from blasts / max|m| {away:.2e}")
+            assert away <= 1e-12, (x, away)
         for k in range(4 + ns):
             if dtype_name == "f64":
-                err = np.max(np.abs(got[k] - ref[k])) / scales[k]
+                err = np.max(np.abs(got[k] - ref[k]) / scales[k])
                 print(f"column {x} var {k} rel err {err:.2e}")
                 assert err <= 1e-12, (x, k, err)
             else:
