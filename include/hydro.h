@@ -40,6 +40,16 @@
  * (non-finite values, rho <= 0) are latched on the device and reported as
  * HYDRO_ENONPHYS by the next call that synchronises.
  *
+ * NAMES.  The five calls the method needs are hydro_create, hydro_compute_dt,
+ * hydro_sweep, hydro_step and hydro_conserved_totals.  Three calls around them
+ * differ from the first sketch of this interface:
+ *   - hydro_batch_layout replaces a call that returned only the batch
+ *     buffer's element count; it also returns each grid's offset and pitch.
+ *   - hydro_mlp_grad replaces a separate backward call: it fuses the forward
+ *     pass, the loss and the backward pass, so activations never reach memory.
+ *   - The network and its gradient are a packed device buffer (void *) and a
+ *     flat float array, not C structs.  Adam's settings are plain arguments.
+ *
  * STREAMS.  All device work of a handle runs on the stream given to
  * hydro_bind, in order.  hydro_sweep and hydro_step never synchronise and
  * keep dt on the device, so they can be captured into a HIP graph;
@@ -124,7 +134,10 @@ typedef struct {
   long long interfaces;                  /* Riemann problems solved         */
   long long hist[HYDRO_MAX_NITER + 1];   /* hist[k]: converged after k
                                             iterations; hist[0]: iteration
-                                            cap reached unconverged         */
+                                            cap reached unconverged;
+                                            hist[HYDRO_MAX_NITER] also holds
+                                            longer counts (a failed learned
+                                            start adds up to 4 to the cap)  */
   long long fallbacks;                   /* learned guess rejected          */
   long long wave_hist[HYDRO_MAX_NITER + 1]; /* groups of interfaces a wave
                                             solves together (up to 64) by
@@ -145,7 +158,10 @@ typedef struct {
   int cached;         /* 1: reused an earlier tuning of the same grid shapes     */
 } hydro_tune_t;
 
-/* Create a solver for an nx x ny grid (both >= 2) of an ideal gas with ratio
+/* Paper, Section 1 (the problem: a fixed rectangular 2D domain, the
+ * compressible Euler equations of an ideal gas, finite volumes) and Figure 5
+ * (boundary conditions applied every step).
+ * Create a solver for an nx x ny grid (both >= 2) of an ideal gas with ratio
  * of specific heats gamma > 1, Courant number 0 < cfl <= 1 and boundary type
  * bc (one of HYDRO_BC_*, applied on all four sides).  Allocates the handle's
  * small device scratch on the current HIP device.  Returns NULL on error
@@ -166,7 +182,9 @@ const char *hydro_last_error(void);
  * the flow.  Only before hydro_bind (HYDRO_ESTATE after). */
 int hydro_set_scalars(hydro_t *h, int n);
 
-/* Bind the state U (device pointer, layout above, pitch in elements) of type
+/* Paper, Figure 5 (U(i,j), the 2D buffer of conservative variables that every
+ * sweep reads and writes back).
+ * Bind the state U (device pointer, layout above, pitch in elements) of type
  * dtype and the HIP stream (hipStream_t; NULL = default stream) all later
  * work runs on.  Rebinding is allowed; it invalidates the fused max speed, so
  * the next step recomputes dt from U.  Call it again (or hydro_invalidate)
@@ -177,28 +195,46 @@ int hydro_bind(hydro_t *h, void *U, long pitch, int dtype, void *hip_stream);
  * changed outside the library). */
 int hydro_invalidate(hydro_t *h);
 
+/* Paper, Section 1 (the limiter, the Riemann solver [4] and the scheme [5]
+ * are delegated to references): the readings and options of hydro_options_t.
+ * Set or read the solver options of a handle; a change drops any captured
+ * graph.  Invalid values return HYDRO_EINVAL and leave the options as they
+ * were. */
 int hydro_set_options(hydro_t *h, const hydro_options_t *o);
 int hydro_get_options(const hydro_t *h, hydro_options_t *o);
 
-/* Time step from the bound state: dt = cfl * h / max over cells of
+/* Paper, Figure 5 (one dt per time step n, shared by both directional
+ * sweeps); the paper does not give the formula, and the CFL bound below is
+ * the reading taken.
+ * Time step from the bound state: dt = cfl * h / max over cells of
  * max(|u|+c, |v|+c).  Stores dt on the device for later sweeps and returns
  * it (> 0), or a negative error code.  Synchronises the stream. */
 double hydro_compute_dt(hydro_t *h);
 
-/* One directional sweep (HYDRO_DIR_X: rows, HYDRO_DIR_Y: columns) of the
+/* Paper, Section 1 (a one-dimensional second-order Godunov update along one
+ * direction, a Riemann problem at every interface), Figures 1 and 2 (cell i
+ * reads cells i-2..i+2 of its pencil only) and Figure 5 (per pencil READ,
+ * COMPUTE: primitive variables, Riemann problems, incoming fluxes, WRITE).
+ * One directional sweep (HYDRO_DIR_X: rows, HYDRO_DIR_Y: columns) of the
  * bound state with the stored dt, boundary conditions applied along that
  * direction (two ghost cells per side).  Asynchronous.  Does not advance the
  * clock. */
 int hydro_sweep(hydro_t *h, int dir);
 
-/* One time step: dt from the current state (taken from the max wave speed
+/* Paper, Section 1 (directional splitting: at each time step the 1D scheme
+ * runs along each direction in turn) and Figure 5 (boundary conditions, the
+ * loop over one direction's pencils, then the other's).
+ * One time step: dt from the current state (taken from the max wave speed
  * fused into the previous step's second sweep when still valid, otherwise
  * from a reduction over U), then the x-sweep and the y-sweep (with
  * HYDRO_ORDER_ALTERNATE: the y-sweep first on odd steps), both with that dt;
  * t += dt, step += 1 on the device.  Asynchronous, no host synchronisation. */
 int hydro_step(hydro_t *h);
 
-/* out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E, then the
+/* Paper, Section 1 (finite-volume form of the Euler equations: cell values
+ * are averages of conserved quantities, so their sums times the cell area
+ * are the domain's mass, momentum and energy).
+ * out[k] = sum over cells of U_k * h^2 (k = rho, rho u, rho v, E, then the
  * passive scalars' rho X: 4 + ns values), summed in FP64 in a fixed order
  * (deterministic), also for float32 states.  Synchronises the stream. */
 int hydro_conserved_totals(hydro_t *h, double *out);
@@ -208,7 +244,8 @@ int hydro_get_clock(hydro_t *h, double *t, long *step, double *dt);
 /* Set the device clock (checkpoint restart); dt is kept.  Asynchronous. */
 int hydro_set_clock(hydro_t *h, double t, long step);
 
-/* Advance nsteps time steps by replaying a HIP graph of nsteps consecutive
+/* Paper, Figure 5 (the loop over time steps n), as one captured unit.
+ * Advance nsteps time steps by replaying a HIP graph of nsteps consecutive
  * hydro_step calls, captured on the bound stream at the first call (and again
  * after hydro_bind, hydro_set_options or a different nsteps).  The bound
  * stream must not be the legacy default stream (capture is not allowed

@@ -62,9 +62,13 @@ __device__ __forceinline__ void fold_max(unsigned long long* acc, double v) {
 // Newton statistics of one wave's interfaces (valid lanes): the histogram of
 // key (iterations to convergence, 0 = unconverged) per interface, and of the
 // wave's largest iteration count `iters` (iterations run, the cap for an
-// unconverged interface), which is what the wave's time follows.
+// unconverged interface), which is what the wave's time follows.  Both bins
+// are clamped to kMaxIter: a learned start that fails its residual test adds
+// up to 4 iterations to the full cap, so counts above kMaxIter land in the
+// last bin instead of past the array.
 __device__ __forceinline__ void count_newton(DevState* st, bool valid, int key, int iters) {
   const int lane = threadIdx.x & (kWave - 1);
+  key = min(key, kMaxIter);
   bool mine = valid;
   unsigned long long all = __ballot(valid);
   if (all != 0ull && lane == __ffsll((long long)all) - 1)

@@ -281,6 +281,29 @@ def test_invalid_network_falls_back(torch_cuda, orc):
     assert rel_err(h.get_state(), ref) <= TOL64
 
 
+def test_iteration_histogram_stays_in_range(torch_cuda, trained):
+    """Newton cap 32 and a test no iterate meets (tol 1e-300): every learned
+    start fails its residual test after 4 iterations and restarts with the
+    full cap, so counts reach 36.  They land in the last bin of the per-
+    interface histogram; no count spills into the per-wave histogram (no
+    wave runs fewer than 5 iterations, so its first bins stay empty)."""
+    net, _ = trained
+    from paper_2106_13465_amd.hydro import Hydro
+
+    U = inputs.random_states(100, 70, seed=15, rough=0.6)
+    h = Hydro(100, 70, 1.4, 0.8, 3)
+    h.set_state(U)
+    h.set_mlp(net)
+    h.set_options(guess=1, stats=1, learned_gate=0.0, niter=32, tol=1e-300)
+    h.step(1)
+    s = h.stats()
+    print("hist", s["hist"], "wave_hist", s["wave_hist"], flush=True)
+    assert sum(s["hist"]) == s["interfaces"] > 0
+    assert sum(s["wave_hist"][:5]) == 0
+    assert sum(s["wave_hist"]) > 0
+    assert s["fallbacks"] > 0.9 * s["interfaces"]
+
+
 def test_logger_records(torch_cuda, orc):
     from paper_2106_13465_amd.hydro import Hydro
 
