@@ -14,7 +14,8 @@
  *                in place (READ into a buffer, COMPUTE, WRITE back), and
  *                before writing a segment it waits until its two neighbours
  *                along the sweep have READ the same pencil, through shared
- *                per-thread counters of pencils read (busy wait with flushes).
+ *                per-thread counters of pencils read (busy wait with flushes;
+ *                the counters are sequentially consistent atomics).
  *   tasks        (Sections 5 and 6, Figure 10): one task per column of
  *                subdomains (subdomains that share a range of pencils); in
  *                it, one task per interface between consecutive subdomains
@@ -142,8 +143,13 @@ static void coarse_sweep(double *U, int nx, int ny, int dir, double lam, const o
       const int r = line - l0 + 1; /* pencils read once this one is */
       /* (1) READ, then publish the count */
       read_segment(U, nx, ny, nv, dir, line, a, b, c->bc, 0, 0, w);
+      /* The counter is a sequentially consistent atomic: its store releases
+       * the READ above, and a neighbour's load that sees it acquires it, so
+       * that READ happens before the neighbour's WRITE of the same cells.
+       * The flushes alone (fences around relaxed atomics) order nothing
+       * after the load that ends the wait. */
 #pragma omp flush
-#pragma omp atomic write
+#pragma omp atomic write seq_cst
       nread[t] = r;
 #pragma omp flush
       /* (2) COMPUTE */
@@ -155,7 +161,7 @@ static void coarse_sweep(double *U, int nx, int ny, int dir, double lam, const o
         for (;;) {
           int v;
 #pragma omp flush
-#pragma omp atomic read
+#pragma omp atomic read seq_cst
           v = nread[o];
           if (v >= r) break;
         }
