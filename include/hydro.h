@@ -239,6 +239,46 @@ int hydro_step(hydro_t *h);
  * (deterministic), also for float32 states.  Synchronises the stream. */
 int hydro_conserved_totals(hydro_t *h, double *out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * One time step of hydro_step (dt from the max wave speed of U, then the
+ * x-sweep and the y-sweep with that dt) for n independent grids held in
+ * caller buffers, with no handle and no device allocation: the per-grid
+ * descriptors and device state the kernels need live in a static device
+ * array inside the library (one copy per GPU, about 12 KB, held until the
+ * process ends), resolved on the first call on each device.  Default
+ * options (minmod, two-shock solver, Newton cap 10, tol 1e-8, two-rarefaction
+ * guess, x then y) and the default launch shape; no clock, statistics,
+ * passive scalars or learned guess.
+ *   n                  1..HYDRO_NOALLOC_MAX_GRIDS grids (more: HYDRO_EINVAL,
+ *                      the size of the static array)
+ *   nx, ny, bc         host arrays [n]: grid sides (>= 2) and HYDRO_BC_*
+ *   offsets, pitches   host arrays [n]: element offset of grid g's plane 0
+ *                      and its row pitch (>= nx[g]); grid g occupies
+ *                      [offsets[g], offsets[g] + 4 ny[g] pitches[g]) of each
+ *                      buffer in the layout of a single grid; grids must not
+ *                      overlap
+ *   dtype              HYDRO_F64 or HYDRO_F32, all three buffers
+ *   U                  device, input: the state at the start of the step
+ *   U_half             device, output: the state after the x-sweep; must not
+ *                      overlap U or U_out
+ *   U_out              device, output: the state after the step; may be U
+ *                      itself (in-place step), else must not overlap it
+ *   dt_out             device array [n] or NULL, output: the dt grid g
+ *                      advanced by, NaN if a sweep of grid g produced a
+ *                      non-physical state
+ *   hip_stream         hipStream_t the work is enqueued on (NULL: default)
+ * All buffers are caller-owned.  Asynchronous: returns after enqueueing (no
+ * synchronisation), HYDRO_EINVAL for bad arguments, HYDRO_EDEVICE for a HIP
+ * error.  Every call on one GPU reuses that GPU's static array: calls that
+ * overlap in time on one GPU (other streams or host threads) race and must
+ * be serialised by the caller. */
+#define HYDRO_NOALLOC_MAX_GRIDS 16
+int hydro_step_noalloc(int n, const int *nx, const int *ny, const int *bc,
+                       const long long *offsets, const long *pitches, int dtype, double gamma,
+                       double cfl, const void *U, void *U_half, void *U_out, double *dt_out,
+                       void *hip_stream);
+
 /* Simulated time, steps taken and the last dt (device clock).  Synchronises. */
 int hydro_get_clock(hydro_t *h, double *t, long *step, double *dt);
 /* Set the device clock (checkpoint restart); dt is kept.  Asynchronous. */

@@ -15,6 +15,7 @@ HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_GUESS_PTR, HYDRO_GUESS_MLP = 0, 1
 HYDRO_OK, HYDRO_EINVAL, HYDRO_ENOMEM, HYDRO_EDEVICE, HYDRO_ENONPHYS, HYDRO_ESTATE = 0, -1, -2, -3, -4, -5
 HYDRO_MAX_NITER = 32
+HYDRO_NOALLOC_MAX_GRIDS = 16
 HYDRO_PHASE_DT, HYDRO_PHASE_SWEEP_X, HYDRO_PHASE_SWEEP_Y, HYDRO_NPHASES = 0, 1, 2, 3
 PHASE_NAMES = ("dt", "sweep_x", "sweep_y")
 
@@ -103,6 +104,9 @@ SIGNATURES = {
     "hydro_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hydro_get_profile": (ctypes.c_int, [_vp, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "hydro_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(hydro_tune_t), ctypes.c_int]),
+    "hydro_step_noalloc": (ctypes.c_int, [ctypes.c_int, _I, _I, _I, _LL, _L, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                          _vp]),
     # learned guess
     "hydro_mlp_dev_bytes": (ctypes.c_size_t, []),
     "hydro_mlp_pack": (ctypes.c_int, [_vp, _vp, _vp]),

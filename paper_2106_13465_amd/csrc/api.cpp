@@ -20,7 +20,7 @@
 struct hydro_s : hydro::Plan {};
 struct hydro_batch_s : hydro::Plan {};
 
-namespace {
+namespace hydro {
 
 thread_local char g_err[512] = "";
 
@@ -31,6 +31,13 @@ int fail(int code, const char* fmt, ...) {
   va_end(ap);
   return code;
 }
+
+}  // namespace hydro
+
+namespace {
+
+using hydro::fail;
+using hydro::g_err;
 
 int dev_fail(hipError_t e, const char* what) {
   return fail(HYDRO_EDEVICE, "%s: %s", what, hipGetErrorString(e));

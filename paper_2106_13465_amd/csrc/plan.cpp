@@ -12,8 +12,6 @@
 
 namespace hydro {
 
-namespace {
-
 template <typename T>
 Gas<T> make_gas(double g, const hydro_options_t& o) {
   Gas<T> G;
@@ -56,6 +54,20 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   }
   return G;
 }
+template Gas<double> make_gas<double>(double, const hydro_options_t&);
+template Gas<float> make_gas<float>(double, const hydro_options_t&);
+
+hydro_options_t default_options() {
+  hydro_options_t o;
+  std::memset(&o, 0, sizeof o);
+  o.niter = 10;
+  o.tol = 1e-8;
+  o.guess = HYDRO_GUESS_PTR;
+  o.learned_gate = HYDRO_LEARNED_GATE_DEFAULT;
+  return o;
+}
+
+namespace {
 
 template <typename T>
 Batch<T> batch_of(const Plan& p, const void* src, void* dst, int seg, long long items) {
@@ -147,11 +159,7 @@ hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_
   bc.assign(bc_, bc_ + n);
   gamma = gamma_;
   cfl = cfl_;
-  std::memset(&opt, 0, sizeof opt);
-  opt.niter = 10;
-  opt.tol = 1e-8;
-  opt.guess = HYDRO_GUESS_PTR;
-  opt.learned_gate = HYDRO_LEARNED_GATE_DEFAULT;
+  opt = default_options();
   HIP_TRY(hipGetDevice(&device));
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&

@@ -105,4 +105,17 @@ struct Plan {
 // Row pitch (elements) padded to 256 bytes.
 long padded_pitch(int nx, int dtype);
 
+// Sets the calling thread's hydro_last_error message (printf format) and
+// returns code.
+int fail(int code, const char* fmt, ...);
+
+// Solver options of a new handle: Newton cap 10, tolerance 1e-8, the
+// two-rarefaction guess, minmod, x then y, the two-shock solver.
+hydro_options_t default_options();
+
+// Gas constants and solver settings of the sweep kernels for ratio of
+// specific heats g and options o, in the kernel's arithmetic type.
+template <typename T>
+Gas<T> make_gas(double g, const hydro_options_t& o);
+
 }  // namespace hydro

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (HYDRO_BC_OUTFLOW, HYDRO_BC_PERIODIC, HYDRO_BC_REFLECT, HYDRO_DIR_X,
                    HYDRO_DIR_Y, HYDRO_F32, HYDRO_F64, HydroError, check)
 
-__all__ = ["Hydro", "HydroBatch", "HydroError", "BC", "DIR_X", "DIR_Y"]
+__all__ = ["Hydro", "HydroBatch", "HydroError", "BC", "DIR_X", "DIR_Y", "step_noalloc"]
 
 BC = {"reflect": HYDRO_BC_REFLECT, "outflow": HYDRO_BC_OUTFLOW, "periodic": HYDRO_BC_PERIODIC}
 DIR_X, DIR_Y = HYDRO_DIR_X, HYDRO_DIR_Y
@@ -366,3 +366,33 @@ class HydroBatch:
         n = (ctypes.c_longlong * _lib.HYDRO_NPHASES)()
         check(self.lib.hydro_batch_get_profile(self.handle, ms, n, int(reset)))
         return _profile_dict(ms, n)
+
+
+def step_noalloc(U: torch.Tensor, U_half: torch.Tensor, U_out: torch.Tensor, shapes, offsets,
+                 pitches, bc, gamma: float = 1.4, cfl: float = 0.8,
+                 dt_out: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> None:
+    """One time step of up to HYDRO_NOALLOC_MAX_GRIDS grids through
+    hydro_step_noalloc (no handle, no device allocation).  U, U_half, U_out are
+    flat device tensors of one dtype holding the grids at ``offsets`` with row
+    ``pitches``; U_out may be U.  ``dt_out`` (float64, one per grid) receives
+    each grid's dt.  Enqueued on ``stream`` (default: the current stream)."""
+    lib = _lib.load()
+    if U.dtype not in _DTYPE or U_half.dtype != U.dtype or U_out.dtype != U.dtype:
+        raise ValueError("U, U_half, U_out: one dtype, float64 or float32")
+    n = len(shapes)
+    bcs = [_bc_code(bc)] * n if not isinstance(bc, (list, tuple)) else [_bc_code(b) for b in bc]
+    nx = (ctypes.c_int * n)(*[int(s[0]) for s in shapes])
+    ny = (ctypes.c_int * n)(*[int(s[1]) for s in shapes])
+    bcc = (ctypes.c_int * n)(*bcs)
+    offs = (ctypes.c_longlong * n)(*[int(o) for o in offsets])
+    pit = (ctypes.c_long * n)(*[int(p) for p in pitches])
+    if dt_out is not None and (dt_out.dtype != torch.float64 or dt_out.numel() < n):
+        raise ValueError("dt_out: float64 tensor of at least one value per grid")
+    s = stream if stream is not None else torch.cuda.current_stream(U.device)
+    dtp = ctypes.c_void_p(dt_out.data_ptr()) if dt_out is not None else None
+    check(lib.hydro_step_noalloc(n, nx, ny, bcc, offs, pit, _DTYPE[U.dtype], float(gamma),
+                                 float(cfl), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(U_half.data_ptr()),
+                                 ctypes.c_void_p(U_out.data_ptr()), dtp,
+                                 ctypes.c_void_p(s.cuda_stream)))
