@@ -155,9 +155,11 @@ VALU_SUMMARY = {"fourier_blasts": "sweep_fourier_blasts_8192_valu.json"}
 def valu_issue(workload_name: str, kernel: str, dtype_name: str, measured_ms: float):
     """The competing bound beside HBM: the committed instruction-count summary
     gives the sweep's VALU instructions per launch; at 4 cycles per wave64
-    instruction on 1024 SIMDs at 2.4 GHz they need `issue_floor_ms`.  frac =
-    floor / the launch time measured now.  None if missing or taken from
-    different kernel sources."""
+    instruction on 1024 SIMDs they need `issue_floor_ms` at the shader clock
+    the same counter run measured (GRBM_GUI_ACTIVE cycles of the 8 XCDs over
+    the kernel's duration), and `issue_floor_ms_2p4ghz` at the 2.4 GHz peak
+    clock.  frac = floor at the measured clock / the launch time measured now.
+    None if missing or taken from different kernel sources."""
     if workload_name not in VALU_SUMMARY:
         return None
     try:
@@ -170,14 +172,75 @@ def valu_issue(workload_name: str, kernel: str, dtype_name: str, measured_ms: fl
     ent = rec.get("kernels", {}).get(f"{kernel}_{dtype_name}")
     if ent is None:
         return None
-    return {"valu_per_lane_cell": ent["valu_per_lane_cell"], "issue_floor_ms": ent["issue_floor_ms"],
-            "measured_ms": measured_ms, "frac": ent["issue_floor_ms"] / measured_ms}
+    c = ent["counters"]
+    clock_ghz = c["GRBM_GUI_ACTIVE"] / 8.0 / (c["_t"] * 1e-3) / 1e9
+    floor_ms = c["SQ_INSTS_VALU"] * 4.0 / (1024 * clock_ghz * 1e9) * 1e3
+    return {"valu_per_lane_cell": ent["valu_per_lane_cell"], "clock_ghz": clock_ghz,
+            "issue_floor_ms": floor_ms, "issue_floor_ms_2p4ghz": ent["issue_floor_ms"],
+            "measured_ms": measured_ms, "frac": floor_ms / measured_ms,
+            "frac_2p4ghz": ent["issue_floor_ms"] / measured_ms}
 
 
-def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
+def cpu_model() -> str:
+    """Model name of this host's CPU (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def compare_to_oracle(got, ref):
+    """FP64 parity figure and FP32 accuracy figure of a GPU state against the
+    oracle's: per variable the largest difference over the variable's scale
+    (max |.| for rho and E; for the momenta max(max |m|, sqrt(2 rho E)) cell by
+    cell, the scale of a momentum that is a difference of large impulses), and
+    the relative L1 error sum |got - ref| / sum |ref|."""
+    import numpy as np
+
+    got = got.astype(np.float64, copy=False)
+    out = {"max_rel_err": [], "rel_l1": []}
+    for k in range(ref.shape[0]):
+        d = np.abs(got[k] - ref[k])
+        if k in (1, 2):
+            mmax = max(float(np.abs(ref[1]).max()), float(np.abs(ref[2]).max()))
+            scale = np.maximum(mmax, np.sqrt(2.0 * np.abs(ref[0] * ref[3])))
+            out["max_rel_err"].append(float((d / scale).max()))
+        else:
+            out["max_rel_err"].append(float(d.max() / max(float(np.abs(ref[k]).max()), 1e-300)))
+        out["rel_l1"].append(float(d.sum() / max(float(np.abs(ref[k]).sum()), 1e-300)))
+        del d
+    return out
+
+
+def gpu_steps_from(U, bc, dtype_name, nsteps, limiter=0, order=0, riemann=0):
+    """State after nsteps eager steps from U on the GPU (default launch shape;
+    results do not depend on it)."""
+    import torch
+
+    from paper_2106_13465_amd.hydro import Hydro
+
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    _, ny, nx = U.shape
+    h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0", nscalars=U.shape[0] - 4)
+    h.set_options(limiter=limiter, order=order, riemann=riemann)
+    h.set_state(U)
+    h.step(nsteps)
+    out = h.get_state()
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0, state_out=None):
     """The oracle timed on this host: one full step of the whole input on all
     OpenMP threads (the reported value), and one step of its top-left 2048^2
-    corner (same boundary rule) on one thread."""
+    corner (same boundary rule) on one thread.  The state after the full step
+    is appended to state_out when given."""
     import numpy as np
 
     import oracle
@@ -192,6 +255,8 @@ def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
     t0 = time.perf_counter()
     oracle.step(V, c)
     sec = time.perf_counter() - t0
+    if state_out is not None:
+        state_out.append(V)
     del V
     m = min(2048, nx, ny)
     W = np.ascontiguousarray(U[:, :m, :m])
@@ -221,13 +286,154 @@ def cpu_baseline(U, bc_name, limiter=0, order=0, riemann=0):
         schemes[name] = rows
     oracle.set_threads(threads)
     return {"value": 2.0 * nx * ny / sec, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle", "seconds": sec,
+            "cpu_model": cpu_model(), "kind": "oracle", "seconds": sec,
             "sample": f"1 full step (dt, x-sweep, y-sweep) of the same {nx}x{ny} input, FP64, "
                       f"{threads} OpenMP threads over pencils",
             "single_core": {"value": 2.0 * m * m / sec1, "seconds": sec1,
                             "sample": f"1 step of the top-left {m}x{m} corner, 1 thread"},
             "openmp_schemes": {"sample": f"1 step of the top-left {m}x{m} corner per entry",
                                **schemes}}
+
+
+def oracle_cfg(bc_name, limiter=0, order=0, riemann=0, nscalars=0):
+    import oracle
+
+    bc = {"periodic": oracle.BC_PERIODIC, "reflect": oracle.BC_REFLECT,
+          "outflow": oracle.BC_OUTFLOW}[bc_name]
+    return oracle.cfg(bc=bc, limiter=limiter, order=order, riemann=riemann, nscalars=nscalars)
+
+
+def c1_cpu(U, bc_name, steps, state_out):
+    """The point-explosion configuration's own metric: seconds of the whole
+    run (steps time steps) of the FP64 oracle on one core and on every core of
+    this host; both runs give the same state (pencils are independent)."""
+    import numpy as np
+
+    import oracle
+
+    c = oracle_cfg(bc_name)
+    threads = oracle.threads()
+    res = {}
+    finals = []
+    for name, t in (("one_core", 1), ("all_cores", threads)):
+        oracle.set_threads(t)
+        V = U.copy()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            oracle.step(V, c)
+        res[name] = {"threads": t, "seconds": time.perf_counter() - t0}
+        finals.append(V)
+    oracle.set_threads(threads)
+    _, ny, nx = U.shape
+    state_out.append(finals[0])
+    return {"value": res["all_cores"]["seconds"], "unit": "s (whole run)", "cores": threads,
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"the whole run: {steps} steps of the {nx}x{ny} input, FP64",
+            "one_core_seconds": res["one_core"]["seconds"],
+            "all_cores_seconds": res["all_cores"]["seconds"],
+            "cell_updates_per_s_all_cores": 2.0 * nx * ny * steps / res["all_cores"]["seconds"],
+            "cell_updates_per_s_one_core": 2.0 * nx * ny * steps / res["one_core"]["seconds"],
+            "one_core_equals_all_cores_bitwise": bool(np.array_equal(finals[0], finals[1]))}
+
+
+STRONG_FAMILY = {"p_decades": 4.0, "rho_decades": 2.0, "speed": 3.0}
+
+
+def bench_strong(args) -> dict:
+    """Strong jumps, the regime where the Riemann solve iterates: 4096^2 cells
+    of independent random states (p over 4 decades, rho over 2, |u|, |v| up to
+    3), periodic.  One step from the same input, repeated: the per-sweep times
+    and the iteration histogram of that step, FP64 and FP32, against the
+    oracle's step of the whole grid."""
+    import numpy as np
+    import torch
+
+    from paper_2106_13465_amd import inputs
+    from paper_2106_13465_amd.hydro import Hydro
+
+    n = args.size or 4096
+    reps = args.steps if args.steps_given else 20
+    print(f"# generating strong_jumps {n}^2", file=sys.stderr, flush=True)
+    U = inputs.strong_jumps(n, n, 32, **STRONG_FAMILY)
+    cells = n * n
+    desc = (f"strong_jumps {n}x{n}: independent random states per cell, rho log-uniform over 2 "
+            "decades, p over 4, u, v uniform in [-3, 3] (seed 32); periodic; one step from "
+            "this input, repeated")
+    results = {}
+    for dn in ("f64", "f32"):
+        print(f"# gpu {dn}: {reps} x (reset, 1 step)", file=sys.stderr, flush=True)
+        dtype = torch.float64 if dn == "f64" else torch.float32
+        elem = 8 if dn == "f64" else 4
+        h = Hydro(n, n, 1.4, 0.8, "periodic", dtype=dtype, device="cuda:0")
+        h.set_state(U)
+        tune = None if args.no_autotune else h.autotune(use_cache=True)
+        h.set_state(U)
+        h.set_options(stats=1)
+        h.stats(reset=True)
+        h.step(1)
+        it = h.stats(reset=True)
+        h.set_options(stats=0)
+        got = h.get_state()
+        h.set_profiling(True)
+        steps_ms = []
+        h.profile(reset=True)
+        for _ in range(reps):
+            h.set_state(U)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(h.stream)
+            h.step(1)
+            b.record(h.stream)
+            torch.cuda.synchronize()
+            steps_ms.append(a.elapsed_time(b))
+        prof = h.profile(reset=True)
+        h.set_profiling(False)
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+        hist = it["hist"]
+        conv = sum(hist[1:])
+        wh = it["wave_hist"]
+        ms = float(np.median(steps_ms))
+        results[dn] = {
+            "value": 2.0 * cells / (ms * 1e-3), "ms_per_step": ms,
+            "sweeps": {"x": sweep_record(cells, elem, prof["sweep_x"]),
+                       "y": sweep_record(cells, elem, prof["sweep_y"])},
+            "launch_shape": tune,
+            "newton": {"interfaces": it["interfaces"], "unconverged": hist[0],
+                       "mean_iterations": sum(k * m for k, m in enumerate(hist) if k > 0)
+                       / max(conv, 1),
+                       "hist": {str(k): m for k, m in enumerate(hist) if m},
+                       "wave_mean_max_iterations": sum(k * m for k, m in enumerate(wh))
+                       / max(sum(wh), 1),
+                       "wave_hist": {str(k): m for k, m in enumerate(wh) if m}},
+            "state": got}
+    res = results["f64"]
+    sx, sy = res["sweeps"]["x"], res["sweeps"]["y"]
+    dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
+    line = {
+        "metric": METRIC, "value": res["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": reps, "warmup": 0, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nx": n, "ny": n, "bc": "periodic", "gamma": 1.4,
+                   "cfl": 0.8, "limiter": "minmod", "riemann": "two_shock", "newton_cap": 10,
+                   "newton_tol": 1e-8, "parallelism": "single GPU"},
+        "sweeps": res["sweeps"], "launch_shape": res["launch_shape"], "newton": res["newton"],
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
+                     "avg_launch_ms": dom["avg_ms"]},
+        "f32": {k: v for k, v in results["f32"].items() if k != "state"},
+    }
+    line["f32"]["speedup_vs_f64"] = results["f32"]["value"] / res["value"]
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle, whole grid, one step)", file=sys.stderr, flush=True)
+        ref = []
+        line["cpu_baseline"] = cpu_baseline(U, "periodic", state_out=ref)
+        line["vs_oracle_after_1_step"] = {
+            "f64": compare_to_oracle(results["f64"]["state"], ref[0]),
+            "f32": compare_to_oracle(results["f32"]["state"], ref[0])}
+    return line
 
 
 BATCH_WORKLOADS = {
@@ -601,7 +807,7 @@ def main() -> int:
                          "128 blast_corner)")
     ap.add_argument("--workload", default="fourier_blasts",
                     choices=["fourier_blasts", "fourier_smooth", "shear_layer", "blast_corner",
-                             "multiblast_batch", "quadrant_batch", "learned"])
+                             "strong_jumps", "multiblast_batch", "quadrant_batch", "learned"])
     ap.add_argument("--train-records", type=int, default=10_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
@@ -638,6 +844,10 @@ def main() -> int:
         print(json.dumps(bench_learned(args)), flush=True)
         return 0
 
+    if args.workload == "strong_jumps":
+        print(json.dumps(bench_strong(args)), flush=True)
+        return 0
+
     if args.workload in BATCH_WORKLOADS:
         if args.dtype == "f64" and not args.dtype_given:
             args.dtype = "f32"
@@ -648,6 +858,8 @@ def main() -> int:
         args.size = {"fourier_blasts": 8192, "fourier_smooth": 8192, "shear_layer": 4096,
                      "blast_corner": 128}.get(
             args.workload, 8192)
+    if args.workload == "blast_corner" and not args.steps_given:
+        args.steps = 100  # the point-explosion configuration's run length
     print(f"# generating {args.workload} {args.size}^2", file=sys.stderr, flush=True)
     U, bc, desc = workload(args.workload, args.size)
     _, ny, nx = U.shape
@@ -741,9 +953,33 @@ def main() -> int:
                        "rel_l1_vs_f64_after_steps": l1}
     del states
     if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(U, bc, LIMITERS[args.limiter], ORDERS[args.order],
-                                            SOLVERS[args.riemann])
+        opts = (LIMITERS[args.limiter], ORDERS[args.order], SOLVERS[args.riemann])
+        ref = []
+        if args.workload == "blast_corner":
+            # the configuration's own metric: the whole run on the CPU
+            print(f"# cpu baseline (oracle, {args.steps} steps)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = c1_cpu(U, bc, args.steps, ref)
+            line["cpu_baseline"]["gpu_seconds_whole_run"] = res["ms_per_step"] * args.steps * 1e-3
+            nref = args.steps
+        else:
+            print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline(U, bc, *opts, state_out=ref)
+            import oracle
+
+            oracle.step(ref[0], oracle_cfg(bc, *opts, nscalars=nv - 4))
+            nref = 2
+        # the GPU results against the oracle's from the same input: FP64 parity
+        # (max relative error) and the FP32 relative L1 error, whole grid
+        print(f"# gpu vs oracle after {nref} steps", file=sys.stderr, flush=True)
+        cmp = {}
+        for dn in variants:
+            got = gpu_steps_from(U, bc, dn, nref, *opts)
+            cmp[dn] = compare_to_oracle(got, ref[0])
+            del got
+        line["vs_oracle"] = {"steps": nref, "cells": "every cell of the grid", **cmp}
+        if "f32" in line:
+            line["f32"]["rel_l1_vs_oracle"] = cmp["f32"]["rel_l1"]
+        del ref
     print(json.dumps(line), flush=True)
     return 0
 

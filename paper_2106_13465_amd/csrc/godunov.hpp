@@ -43,6 +43,7 @@ struct Gas {
   T rare_coef; // 2 / (gamma - 1)
   int ipow_r;  // 2/(gamma - 1) when it is a small integer (5 for gamma = 1.4), else 0
   T ser[4];    // binomial series of (1 + e)^(-z): coefficients of e, e^2, e^3, e^4
+  T noise;     // FP32: rounding-noise factor of the Newton residual test (0 in FP64)
 };
 
 // |e| bound below which the four-term series of (1 + e)^(-z) is exact to
@@ -293,6 +294,13 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   // one Newton iteration on p; true when converged
   auto newton_step = [&](T& pp) -> bool {
     T dp;
+    // FP32: the residual f(p) is a difference of velocity terms that cancel
+    // at the root, so it is only known to a few ulp of the largest of them;
+    // once |f| is within that rounding noise the iterate is the root to
+    // single precision and further steps only move it by noise (which can
+    // exceed the relative test on strong waves).  at_noise ends the loop
+    // there.  FP64 keeps the plain test.
+    bool at_noise = false;
     if constexpr (RS == 0) {
       // two-shock f(p) = sum_K (p - p_K)/W_K + u_R - u_L with
       // W_K^2 = C_K (1 + gs (p - p_K)/p_K) = rho_K ((gamma-1)/2 p_K + (gamma+1)/2 p);
@@ -302,22 +310,29 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
       const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
       const T izL2 = T(0.5) * (XL + CL) * (iWL * iWL * iWL);
       const T izR2 = T(0.5) * (XR + CR) * (iWR * iWR * iWR);
-      const T usL = L.u - (pp - L.p) * iWL;
-      const T usR = R.u + (pp - R.p) * iWR;
+      const T dL = (pp - L.p) * iWL, dR = (pp - R.p) * iWR;
+      const T usL = L.u - dL;
+      const T usR = R.u + dR;
       dp = (usL - usR) * fm::rcp(izL2 + izR2);
+      if constexpr (sizeof(T) == 4)
+        at_noise = fabs(usL - usR) <=
+                   G.noise * ((fabs(L.u) + fabs(R.u)) + (fabs(dL) + fabs(dR)));
     } else {
       // exact f(p) = f_L(p) + f_R(p) + u_R - u_L
       const T ip = fm::rcp(pp);
       T fL, dL, fR, dR, yL, yR;
       exact_curve(pp, ip, L.r, L.p, cL, izL, G, fL, dL, yL);
       exact_curve(pp, ip, R.r, R.p, cR, izR, G, fR, dR, yR);
-      dp = -(fL + fR + (R.u - L.u)) * fm::rcp(dL + dR);
+      const T f = fL + fR + (R.u - L.u);
+      dp = -f * fm::rcp(dL + dR);
+      if constexpr (sizeof(T) == 4)
+        at_noise = fabs(f) <= G.noise * ((fabs(fL) + fabs(fR)) + (fabs(L.u) + fabs(R.u)));
     }
     // a step from the floor that points below it: the root lies under the
     // floor (f increasing), so the floored star pressure is the floor
     const bool below_floor = pp == pmin && pp + dp < pmin;
     pp = fmax(pp + dp, pmin);
-    return fabs(dp) <= G.tol * pp || below_floor;
+    return fabs(dp) <= G.tol * pp || below_floor || at_noise;
   };
   // The first iteration runs for every interface as straight-line code; the
   // loop only carries the interfaces that need more (or fall back).

@@ -31,6 +31,9 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   // in FP32 the test is floored at 8 ulp of 1.
   const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
   G.tol = T(o.tol > tol_floor ? o.tol : tol_floor);
+  // FP32: the residual counts as rounding noise within 4 ulp of the sum of
+  // the magnitudes of its terms
+  G.noise = T(sizeof(T) == 4 ? 4.0 * 1.1920928955078125e-07 : 0.0);
   G.niter = o.niter;
   G.niter_learned = o.niter < 4 ? o.niter : 4;
   // 1/z = 2 gamma / (gamma - 1); an integer exponent (7 for gamma = 1.4) lets

@@ -224,6 +224,27 @@ def test_fp32_l1(torch_cuda, orc, bc):
         assert l1 < 1e-5
 
 
+@pytest.mark.parametrize("fam", [dict(p_decades=2.0, rho_decades=1.0, speed=2.0),
+                                 dict(p_decades=4.0, rho_decades=2.0, speed=3.0)])
+def test_fp32_strong_jumps_all_converge(torch_cuda, orc, fam):
+    """FP32 on strong jumps: the Newton loop stops once its residual is at
+    rounding level, so no interface runs to the cap, and the step stays
+    within the FP32 L1 bound of the oracle's FP64 step."""
+    U = inputs.strong_jumps(256, 192, 41, **fam)
+    h = make(torch_cuda, U, 3, dtype=torch_cuda.float32, stats=1)
+    h.step(1)
+    s = h.stats()
+    print("fp32 strong jumps", fam, "unconverged", s["hist"][0], "interfaces", s["interfaces"])
+    assert s["interfaces"] == 257 * 192 + 193 * 256
+    assert s["hist"][0] == 0
+    ref = U.copy()
+    orc.step(ref, orc.cfg(bc=3))
+    got = h.get_state().astype(np.float64)
+    for k in range(4):
+        l1 = np.abs(got[k] - ref[k]).sum() / np.abs(ref[k]).sum()
+        assert l1 < 1e-5, (k, l1)
+
+
 @pytest.mark.parametrize("n", [128, 256])
 def test_fp32_error_below_truncation(torch_cuda, orc, n):
     """Equal accuracy: a density wave rho = 1 + 0.2 sin(2 pi (x + y)) carried
