@@ -68,10 +68,11 @@ def workload(name: str, n: int):
 LIMITERS = {"minmod": 0, "mc": 1, "vanleer": 2}
 ORDERS = {"xy": 0, "alternate": 1}
 SOLVERS = {"two_shock": 0, "exact": 1, "hllc": 2}
+YSWEEPS = {"march": 0, "tile": 1}
 
 
 def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True, limiter=0,
-            order=0, riemann=0):
+            order=0, riemann=0, ysweep=0):
     """U has 4 + n planes for n passive scalars."""
     import torch
 
@@ -80,7 +81,7 @@ def run_gpu(U, bc, dtype_name, steps, warmup, seg_x=0, seg_y=0, autotune=True, l
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     _, ny, nx = U.shape
     h = Hydro(nx, ny, 1.4, 0.8, bc, dtype=dtype, device="cuda:0", nscalars=U.shape[0] - 4)
-    h.set_options(limiter=limiter, order=order, riemann=riemann)
+    h.set_options(limiter=limiter, order=order, riemann=riemann, ysweep=ysweep)
     if seg_x or seg_y:
         h.set_options(seg_x=seg_x, seg_y=seg_y)
     h.set_state(U)
@@ -822,6 +823,8 @@ def main() -> int:
                     help="interface solver")
     ap.add_argument("--scalars", type=int, choices=[0, 1], default=0,
                     help="passive scalars carried (a smooth seeded field)")
+    ap.add_argument("--ysweep", choices=sorted(YSWEEPS), default="march",
+                    help="form of the y-sweep kernel: column march (default) or LDS tiles")
     ap.add_argument("--seg-x", type=int, default=0)
     ap.add_argument("--seg-y", type=int, default=0)
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -879,7 +882,7 @@ def main() -> int:
               flush=True)
         h, r = run_gpu(U, bc, dn, args.steps, args.warmup, args.seg_x, args.seg_y,
                        not args.no_autotune, LIMITERS[args.limiter], ORDERS[args.order],
-                       SOLVERS[args.riemann])
+                       SOLVERS[args.riemann], YSWEEPS[args.ysweep])
         elem = 8 if dn == "f64" else 4
         ms_step = r["ms_total"] / args.steps
         sx = sweep_record(cells, elem, r["profile"]["sweep_x"], nv)
@@ -911,7 +914,7 @@ def main() -> int:
     dom_name, dom = ("sweep_x", sx) if sx["avg_ms"] >= sy["avg_ms"] else ("sweep_y", sy)
     # the counter summaries are taken with the default limiter, order and solver
     default_opts = (args.limiter == "minmod" and args.order == "xy" and args.riemann == "two_shock"
-                    and args.scalars == 0)
+                    and args.scalars == 0 and args.ysweep == "march")
     traffic = pmc_traffic(args.workload, dom_name, main_dn) if default_opts else None
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": dom["hbm_gbps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_gbps"] / HBM_PEAK_GBS,
@@ -936,6 +939,7 @@ def main() -> int:
         "config": {"workload": desc, "nx": nx, "ny": ny, "bc": bc, "gamma": 1.4, "cfl": 0.8,
                    "limiter": args.limiter, "sweep_order": args.order,
                    "riemann": args.riemann, "passive_scalars": args.scalars,
+                   "ysweep": args.ysweep,
                    "newton_cap": 10, "newton_tol": 1e-8,
                    "parallelism": "single GPU"},
         "sweeps": res["sweeps"],

@@ -103,11 +103,21 @@ enum { HYDRO_ORDER_XY = 0, HYDRO_ORDER_ALTERNATE = 1 };
  * averages; no iteration, so Riemann statistics and the interface logger
  * record nothing and the learned guess is rejected (HYDRO_EINVAL). */
 enum { HYDRO_RIEMANN_TWO_SHOCK = 0, HYDRO_RIEMANN_EXACT = 1, HYDRO_RIEMANN_HLLC = 2 };
+/* Form of the y-sweep kernel (options.ysweep); same numerics, results equal
+ * to rounding.  HYDRO_YSWEEP_MARCH (default): each thread marches down one
+ * column with the 5-cell stencil in registers, 64 adjacent columns per wave,
+ * so every load and store is one coalesced row access.  HYDRO_YSWEEP_TILE:
+ * 16-column by 64-row tiles are read row-coalesced into LDS, transposed, and
+ * swept one cell per lane with the x-sweep's code (a pencil tile staged in
+ * LDS with its two ghost cells per side); slower on MI355X (more
+ * instructions per cell for a kernel bound by instruction issue). */
+enum { HYDRO_YSWEEP_MARCH = 0, HYDRO_YSWEEP_TILE = 1 };
 
 /* Solver options (hydro_set_options).  Defaults: niter 10, tol 1e-8,
  * guess HYDRO_GUESS_PTR, stats 0, tiles chosen by the library,
  * learned_gate HYDRO_LEARNED_GATE_DEFAULT, limiter HYDRO_LIMITER_MINMOD,
- * order HYDRO_ORDER_XY, riemann HYDRO_RIEMANN_TWO_SHOCK. */
+ * order HYDRO_ORDER_XY, riemann HYDRO_RIEMANN_TWO_SHOCK,
+ * ysweep HYDRO_YSWEEP_MARCH. */
 typedef struct {
   int niter;     /* Newton iteration cap, 1..HYDRO_MAX_NITER              */
   double tol;    /* convergence test |dp| <= tol * p, > 0                  */
@@ -126,6 +136,7 @@ typedef struct {
   int limiter;   /* HYDRO_LIMITER_*                                        */
   int order;     /* HYDRO_ORDER_*                                          */
   int riemann;   /* HYDRO_RIEMANN_*                                        */
+  int ysweep;    /* HYDRO_YSWEEP_*                                         */
 } hydro_options_t;
 
 /* Riemann-solver statistics accumulated since the last reset

@@ -40,6 +40,7 @@ class hydro_options_t(ctypes.Structure):
         ("limiter", ctypes.c_int),
         ("order", ctypes.c_int),
         ("riemann", ctypes.c_int),
+        ("ysweep", ctypes.c_int),
     ]
 
 
@@ -47,6 +48,7 @@ HYDRO_LEARNED_GATE_DEFAULT = 1.0
 HYDRO_LIMITER_MINMOD, HYDRO_LIMITER_MC, HYDRO_LIMITER_VANLEER = 0, 1, 2
 HYDRO_ORDER_XY, HYDRO_ORDER_ALTERNATE = 0, 1
 HYDRO_RIEMANN_TWO_SHOCK, HYDRO_RIEMANN_EXACT, HYDRO_RIEMANN_HLLC = 0, 1, 2
+HYDRO_YSWEEP_MARCH, HYDRO_YSWEEP_TILE = 0, 1
 HYDRO_MAX_SCALARS = 1
 
 

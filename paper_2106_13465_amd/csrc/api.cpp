@@ -119,6 +119,8 @@ int check_options(const hydro::Plan* p, const hydro_options_t* o) {
     return fail(HYDRO_EINVAL, "order %d", o->order);
   if (o->riemann < HYDRO_RIEMANN_TWO_SHOCK || o->riemann > HYDRO_RIEMANN_HLLC)
     return fail(HYDRO_EINVAL, "riemann %d", o->riemann);
+  if (o->ysweep != HYDRO_YSWEEP_MARCH && o->ysweep != HYDRO_YSWEEP_TILE)
+    return fail(HYDRO_EINVAL, "ysweep %d", o->ysweep);
   if (o->riemann == HYDRO_RIEMANN_HLLC && o->guess == HYDRO_GUESS_MLP)
     return fail(HYDRO_EINVAL, "the learned guess needs an iterative solver, not HLLC");
   return HYDRO_OK;

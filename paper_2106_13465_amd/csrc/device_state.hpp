@@ -20,6 +20,9 @@ constexpr int kMaxIter = 32;      // largest Newton cap (HYDRO_MAX_NITER)
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kXOut = kWave - 4;  // x-sweep cells updated per 64-lane segment
 constexpr int kWavesPerBlock = 4;
+constexpr int kTileCols = 16;        // tiled y-sweep: columns per tile
+constexpr int kTileRows = kWave;     // ... rows held per tile (one per lane)
+constexpr int kTileOut = kWave - 4;  // ... rows updated per tile
 constexpr int kMaxTotBlocks = 512;  // partial-sum blocks per grid for totals
 constexpr int kMaxScalars = 1;      // passive scalars (HYDRO_MAX_SCALARS)
 constexpr int kMaxVars = 4 + kMaxScalars;
@@ -71,6 +74,7 @@ struct GridDesc {
   double cfl;
   long long wx0;    // first global wave of this grid in the x-sweep
   long long wy0;    // first global wave of this grid in the y-sweep
+  long long wt0;    // first global tile of this grid in the tiled y-sweep
   long long r0;     // first global row (row-item kernels)
   int tb0;          // first partial block of the totals
   int ntb;          // partial blocks of the totals

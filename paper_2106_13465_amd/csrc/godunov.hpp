@@ -71,11 +71,15 @@ __device__ __forceinline__ Prim<T> cons_to_prim(T U0, T Un, T Ut, T E, const Gas
 }
 
 // minmod: the argument of smaller magnitude if both have the same sign, else 0,
-// as max(min(a, b), min(0, max(a, b))): both positive gives the smaller, both
-// negative the larger (smaller magnitude), opposite signs or a zero give 0
-template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
-  return fmax(fmin(a, b), fmin(T(0), fmax(a, b)));
+// which is the median of (a, b, 0): both positive gives the smaller, both
+// negative the larger (smaller magnitude), opposite signs or a zero give 0.
+// FP32: one v_med3_f32; FP64 (no median instruction) as
+// max(min(a, b), min(0, max(a, b))).
+__device__ __forceinline__ float minmod(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+__device__ __forceinline__ double minmod(double a, double b) {
+  return fmax(fmin(a, b), fmin(0.0, fmax(a, b)));
 }
 
 // Limited slope from the two one-sided differences: LIM 0 minmod, 1 MC,

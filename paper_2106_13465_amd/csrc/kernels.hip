@@ -19,6 +19,8 @@
 //   with a register window of the 5-cell stencil (paper, Figure 2); lanes
 //   run along x, so every load and store of the wave is one coalesced row
 //   access without an LDS transpose.
+// tiled y-sweep (option): the x-sweep's one-lane-per-cell code along the
+//   columns of a 16 x 64 tile transposed through LDS (sweeps.hpp).
 // The last sweep of a step computes the max wave speed of the new state in
 // its epilogue, for the grid's next dt (fused CFL reduction).
 //
@@ -195,6 +197,8 @@ extern template SweepFn<double> sweep_table_ns<double, 0, 1>(int);
 extern template SweepFn<double> sweep_table_ns<double, 1, 1>(int);
 extern template SweepFn<float> sweep_table_ns<float, 0, 1>(int);
 extern template SweepFn<float> sweep_table_ns<float, 1, 1>(int);
+extern template SweepFn<double> sweep_table_ns<double, 2, 1>(int);
+extern template SweepFn<float> sweep_table_ns<float, 2, 1>(int);
 
 template <typename T, int DIR>
 SweepFn<T> sweep_kernel(bool instr, int guess, bool fuse, int limiter, int riemann, int ns) {
@@ -234,6 +238,19 @@ hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(blocks_for(b.items, max_blocks)), dim3(kWave * kWavesPerBlock), 0,
                      s, b, G, ex);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep_y_tile(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                               int guess, unsigned max_blocks, hipStream_t s) {
+  const SweepFn<T> k =
+      sweep_kernel<T, 2>(instr, guess, ex.fuse != 0, G.limiter, G.riemann, b.nv - 4);
+  if (!k) return hipErrorInvalidValue;
+  long long nb = b.items;
+  if (max_blocks > 0 && nb > (long long)max_blocks) nb = max_blocks;
+  hipLaunchKernelGGL(k, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kWave * kWavesPerBlock), 0, s, b,
+                     G, ex);
   return hipGetLastError();
 }
 
@@ -286,6 +303,8 @@ hipError_t launch_clear_stats(DevState* st, int n, hipStream_t s) {
                                         int, unsigned, hipStream_t);                          \
   template hipError_t launch_sweep_y<T>(const Batch<T>&, const Gas<T>&, const Extras&, bool,  \
                                         int, unsigned, hipStream_t);                          \
+  template hipError_t launch_sweep_y_tile<T>(const Batch<T>&, const Gas<T>&, const Extras&,   \
+                                             bool, int, unsigned, hipStream_t);               \
   template int sweep_y_blocks_per_cu<T>(bool, int, bool, int, int, int);                      \
   template hipError_t launch_max_speed<T>(const Batch<T>&, const Gas<T>&, hipStream_t);       \
   template hipError_t launch_copy<T>(const Batch<T>&, hipStream_t);                           \

@@ -8,5 +8,7 @@ template SweepFn<double> sweep_table_ns<double, 0, 1>(int);
 template SweepFn<double> sweep_table_ns<double, 1, 1>(int);
 template SweepFn<float> sweep_table_ns<float, 0, 1>(int);
 template SweepFn<float> sweep_table_ns<float, 1, 1>(int);
+template SweepFn<double> sweep_table_ns<double, 2, 1>(int);
+template SweepFn<float> sweep_table_ns<float, 2, 1>(int);
 
 }  // namespace hydro

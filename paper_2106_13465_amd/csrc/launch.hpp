@@ -21,6 +21,11 @@ hipError_t launch_sweep_x(const Batch<T>& b, const Gas<T>& G, const Extras& ex, 
 template <typename T>
 hipError_t launch_sweep_y(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
                           int guess, unsigned max_blocks, hipStream_t s);
+// The y-sweep through LDS tiles: b.items tiles (GridDesc::wt0 prefixes), one
+// block per tile (max_blocks = 0) or persistent blocks.
+template <typename T>
+hipError_t launch_sweep_y_tile(const Batch<T>& b, const Gas<T>& G, const Extras& ex, bool instr,
+                               int guess, unsigned max_blocks, hipStream_t s);
 // Resident blocks per CU of the y-sweep variant (runtime occupancy query),
 // for sizing its work items to whole rounds of the chip; 0 on error.
 template <typename T>

@@ -197,6 +197,7 @@ hipError_t Plan::init(int ngrids, const int* nx_, const int* ny_, const int* bc_
 hipError_t Plan::upload_descriptors() {
   items_x = 0;
   items_y = 0;
+  items_t = 0;
   for (int g = 0; g < n; ++g) {
     GridDesc& d = desc[g];
     d.off = off.empty() ? 0 : off[g];
@@ -209,6 +210,9 @@ hipError_t Plan::upload_descriptors() {
     const long long ncolg = (nx[g] + kWave - 1) / kWave;
     d.wy0 = items_y;
     items_y += ncolg * ((ny[g] + cfg.seg_y - 1) / cfg.seg_y);
+    d.wt0 = items_t;
+    items_t += (long long)((nx[g] + kTileCols - 1) / kTileCols) *
+               ((ny[g] + kTileOut - 1) / kTileOut);
   }
   HIP_TRY(hipMemcpy(d_desc, desc.data(), sizeof(GridDesc) * n, hipMemcpyHostToDevice));
   drop_graph();
@@ -299,6 +303,9 @@ hipError_t Plan::enqueue_sweep(int dir, bool fuse, const void* src, void* dst) {
     if (dir == HYDRO_DIR_X)
       return launch_sweep_x<double>(batch_of<double>(*this, src, dst, cfg.seg_x, items_x), G, ex,
                                     instr, guess, cfg.blocks_x, stream);
+    if (opt.ysweep == HYDRO_YSWEEP_TILE)
+      return launch_sweep_y_tile<double>(batch_of<double>(*this, src, dst, 0, items_t), G, ex,
+                                         instr, guess, cfg.blocks_y, stream);
     return launch_sweep_y<double>(batch_of<double>(*this, src, dst, cfg.seg_y, items_y), G, ex,
                                   instr, guess, cfg.blocks_y, stream);
   }
@@ -306,6 +313,9 @@ hipError_t Plan::enqueue_sweep(int dir, bool fuse, const void* src, void* dst) {
   if (dir == HYDRO_DIR_X)
     return launch_sweep_x<float>(batch_of<float>(*this, src, dst, cfg.seg_x, items_x), G, ex,
                                  instr, guess, cfg.blocks_x, stream);
+  if (opt.ysweep == HYDRO_YSWEEP_TILE)
+    return launch_sweep_y_tile<float>(batch_of<float>(*this, src, dst, 0, items_t), G, ex, instr,
+                                      guess, cfg.blocks_y, stream);
   return launch_sweep_y<float>(batch_of<float>(*this, src, dst, cfg.seg_y, items_y), G, ex, instr,
                                guess, cfg.blocks_y, stream);
 }
@@ -416,8 +426,8 @@ namespace {
 
 std::mutex g_tune_mu;
 // keyed by dtype, kernel variant (starting guess, limiter, solver, passive
-// scalars) and grid shapes
-using TuneKey = std::tuple<int, int, int, int, int, std::vector<int>>;
+// scalars, y-sweep form) and grid shapes
+using TuneKey = std::tuple<int, int, int, int, int, int, std::vector<int>>;
 std::map<TuneKey, LaunchCfg> g_tune_cache;
 
 TuneKey tune_key(const Plan& p) {
@@ -429,7 +439,7 @@ TuneKey tune_key(const Plan& p) {
     shape.push_back(p.bc[g]);
   }
   const int guess = (p.opt.guess == HYDRO_GUESS_MLP && p.mlp) ? 1 : 0;
-  return {p.dtype, guess, p.opt.limiter, p.opt.riemann, p.nscalars, shape};
+  return {p.dtype, guess, p.opt.limiter, p.opt.riemann, p.nscalars, p.opt.ysweep, shape};
 }
 
 }  // namespace
@@ -566,6 +576,8 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     }
     for (int sy : segy) {
       if (user_seg_y && sy != saved.seg_y) continue;
+      // the tiled y-sweep has fixed tiles: only its block count is tuned
+      if (opt.ysweep == HYDRO_YSWEEP_TILE && sy != segy[0]) continue;
       if (!user_seg_y && sy > 2 * maxny && sy != 32) continue;
       for (unsigned pb : persist) {
         LaunchCfg c = saved;
@@ -580,7 +592,7 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
     best = saved;
     best.seg_x = wx.seg_x;
     best.blocks_x = wx.blocks_x;
-    best.seg_y = wy.seg_y;
+    best.seg_y = opt.ysweep == HYDRO_YSWEEP_TILE ? saved.seg_y : wy.seg_y;
     best.blocks_y = wy.blocks_y;
     guard.done = true;
     std::lock_guard<std::mutex> lk(g_tune_mu);

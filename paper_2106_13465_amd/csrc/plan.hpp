@@ -42,7 +42,7 @@ struct Plan {
   std::vector<GridDesc> desc;
   double* partials = nullptr;
   int tot_blocks = 0;
-  long long items_x = 0, items_y = 0, rows = 0;
+  long long items_x = 0, items_y = 0, items_t = 0, rows = 0;
   // bound state
   void* U = nullptr;
   void* V = nullptr;  // second buffer (owned)

@@ -147,10 +147,10 @@ __device__ __forceinline__ long long wave_stride() {
 
 // Last grid whose first item is <= w (prefix tables start at 0 and never
 // decrease).
-enum class Key { X, Y, Row };
+enum class Key { X, Y, Tile, Row };
 template <Key K>
 __device__ __forceinline__ long long key_of(const GridDesc& d) {
-  return K == Key::X ? d.wx0 : (K == Key::Y ? d.wy0 : d.r0);
+  return K == Key::X ? d.wx0 : (K == Key::Y ? d.wy0 : (K == Key::Tile ? d.wt0 : d.r0));
 }
 template <Key K>
 __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) {
@@ -190,7 +190,92 @@ struct SweepOcc {
   static constexpr int cap_y = RS == 1 && !f32 ? 2 : f32 && (RS == 2 || NS > 0) ? 5 : 8;
   static constexpr int x = kOcc[v] < cap_x ? kOcc[v] : cap_x;
   static constexpr int y = kOcc[4 + v] < cap_y ? kOcc[4 + v] : cap_y;
+  // tiled y-sweep (the x-sweep's code plus the tile loop): the FP64 default
+  // variant at 4 waves (5 spilled; the two ran within 0.4% of each other in
+  // a single-grid build), the exact solver at 2, the other FP64 variants at
+  // 3, FP32 as the x-sweep
+  static constexpr int t = f32 ? x : (RS == 1 ? 2 : (GUESS == 0 && NS == 0 ? 4 : 3));
 };
+
+// Conservative state of the cell one lane holds: density, normal and
+// transverse momentum, energy, and rho X of the passive scalar (NS).
+template <typename T>
+struct Lane {
+  T r, n, t, e, s;
+};
+
+// One pencil segment of 64 cells held one cell per lane: lane l holds cell
+// c0 - 2 + l, so lanes 2..61 are the 60 cells the segment updates and lanes
+// 0, 1, 62, 63 their ghost or neighbour cells (cells past the pencil's end
+// hold clamped copies that no updated cell depends on).  Neighbours come by
+// cross-lane shuffles (primitive variables for the slopes, left face states
+// for the Riemann problem at each lane's right interface, fluxes for the
+// update).  On return c holds the lane's updated cell (meaningful in lanes
+// 2..61).  iface_valid marks the lanes whose right interface this segment
+// owns (statistics and logger, INSTR); log_key identifies it for the logger.
+// The x-sweep runs it along rows, the tiled y-sweep along columns of a tile
+// transposed through LDS.
+template <typename T, bool INSTR, int GUESS, int LIM, int RS, int NS>
+__device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& G,
+                                               const Extras& ex, DevState* st, bool iface_valid,
+                                               unsigned long long log_key) {
+  // COMPUTE: primitive variables, slopes, half-step face states
+  T ir;
+  const Prim<T> q = cons_to_prim(c.r, c.n, c.t, c.e, G, ir);
+  const Prim<T> ql = from_left(q);
+  const Prim<T> qr = from_right(q);
+  Prim<T> dq;
+  dq.r = limit<LIM>(q.r - ql.r, qr.r - q.r);
+  dq.u = limit<LIM>(q.u - ql.u, qr.u - q.u);
+  dq.t = limit<LIM>(q.t - ql.t, qr.t - q.t);
+  dq.p = limit<LIM>(q.p - ql.p, qr.p - q.p);
+  Prim<T> qm, qp;
+  trace(q, ir, dq, lam, G, qm, qp);
+  // passive scalar X = rho X / rho: limited slope, half-step faces with
+  // the advective source -u dX
+  T xm = T(0), xp = T(0);
+  if constexpr (NS > 0) {
+    const T X = c.s * ir;
+    const T dX = limit<LIM>(X - from_left(X), from_right(X) - X);
+    const T hs = T(-0.5) * lam * q.u * dX;
+    xm = X - T(0.5) * dX + hs;
+    xp = X + T(0.5) * dX + hs;
+  }
+
+  // Riemann problem at this lane's right interface
+  const Prim<T> qm_next = from_right(qm);
+  T p_learned = T(0);
+  if (GUESS)
+    p_learned = learned_guess<T>(ex.mlp, qp, qm_next, ex.gamma, ex.gate_kappa, ex.gate_theta2);
+  int iters;
+  bool conv, fb, left;
+  T pstar;
+  // FP64: the series form of the guess's power in smooth waves (measured
+  // 4% faster on the x-sweep; no gain in FP32 or in the y-sweep's loop)
+  const Flux<T> F = riemann_flux<RS, T, sizeof(T) == 8>(qp, qm_next, G, p_learned, iters, conv,
+                                                        fb, pstar, left);
+  const Flux<T> Fl = from_left(F);  // the lane's left interface
+  // scalar flux: mass flux times X on the side of the contact at x/t = 0
+  T FX = T(0), FXl = T(0);
+  if constexpr (NS > 0) {
+    const T xm_next = from_right(xm);
+    FX = F.m * (left ? xp : xm_next);
+    FXl = from_left(FX);
+  }
+
+  if (INSTR) {
+    count_newton(st, iface_valid, conv ? iters : 0, iters);
+    if (GUESS) count_flag(&st->fallbacks, iface_valid && fb);
+    if (ex.log) log_interface(ex, iface_valid, qp, qm_next, pstar, log_key);
+  }
+
+  // conservative update of the lane's cell
+  c.r = c.r + lam * (Fl.m - F.m);
+  c.n = c.n + lam * (Fl.n - F.n);
+  c.t = c.t + lam * (Fl.t - F.t);
+  c.e = c.e + lam * (Fl.e - F.e);
+  if constexpr (NS > 0) c.s = c.s + lam * (FXl - FX);
+}
 
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
@@ -216,85 +301,35 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_
       if (seg >= nseg) break;
       const int x0 = seg * kXOut;
       const int i = x0 - 2 + lane;  // cell of this lane, in [-2, nx+1] when used
+      // READ, with the boundary rule in the index remap
       bool flip;
       const int src = ghost_source(min(i, d.nx + 1), d.nx, d.bc, flip);
-      T u0 = rowp[src];
-      T un = rowp[P + src];
-      T ut = rowp[2 * P + src];
-      T e = rowp[3 * P + src];
-      T sx = T(0);  // rho X of the passive scalar (NS)
-      if constexpr (NS > 0) sx = rowp[4 * P + src];
-      if (flip) un = -un;
+      Lane<T> c;
+      c.r = rowp[src];
+      c.n = rowp[P + src];
+      c.t = rowp[2 * P + src];
+      c.e = rowp[3 * P + src];
+      c.s = T(0);
+      if constexpr (NS > 0) c.s = rowp[4 * P + src];
+      if (flip) c.n = -c.n;
 
-      // COMPUTE: primitive variables, slopes, half-step face states
-      T ir;
-      const Prim<T> q = cons_to_prim(u0, un, ut, e, G, ir);
-      const Prim<T> ql = from_left(q);
-      const Prim<T> qr = from_right(q);
-      Prim<T> dq;
-      dq.r = limit<LIM>(q.r - ql.r, qr.r - q.r);
-      dq.u = limit<LIM>(q.u - ql.u, qr.u - q.u);
-      dq.t = limit<LIM>(q.t - ql.t, qr.t - q.t);
-      dq.p = limit<LIM>(q.p - ql.p, qr.p - q.p);
-      Prim<T> qm, qp;
-      trace(q, ir, dq, lam, G, qm, qp);
-      // passive scalar X = rho X / rho: limited slope, half-step faces with
-      // the advective source -u dX
-      T xm = T(0), xp = T(0);
-      if constexpr (NS > 0) {
-        const T X = sx * ir;
-        const T dX = limit<LIM>(X - from_left(X), from_right(X) - X);
-        const T hs = T(-0.5) * lam * q.u * dX;
-        xm = X - T(0.5) * dX + hs;
-        xp = X + T(0.5) * dX + hs;
-      }
+      // interfaces owned by this segment: x0-1/2 (first segment only) and
+      // the right interfaces of its cells
+      const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
+      pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
+          c, lam, G, ex, st, valid,
+          ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+              ((unsigned long long)row * (d.nx + 1) + (i + 1)) * 2ull);
 
-      // Riemann problem at this lane's right interface i+1/2
-      const Prim<T> qm_next = from_right(qm);
-      T p_learned = T(0);
-      if (GUESS)
-        p_learned = learned_guess<T>(ex.mlp, qp, qm_next, ex.gamma, ex.gate_kappa, ex.gate_theta2);
-      int iters;
-      bool conv, fb, left;
-      T pstar;
-      // FP64: the series form of the guess's power in smooth waves (measured
-      // 4% faster on the x-sweep; no gain in FP32 or in the y-sweep's loop)
-      const Flux<T> F = riemann_flux<RS, T, sizeof(T) == 8>(qp, qm_next, G, p_learned, iters,
-                                                            conv, fb, pstar, left);
-      const Flux<T> Fl = from_left(F);  // interface i-1/2
-      // scalar flux: mass flux times X on the side of the contact at x/t = 0
-      T FX = T(0), FXl = T(0);
-      if constexpr (NS > 0) {
-        const T xm_next = from_right(xm);
-        FX = F.m * (left ? xp : xm_next);
-        FXl = from_left(FX);
-      }
-
-      if (INSTR) {
-        // interfaces owned by this segment: x0-1/2 (first segment only) and
-        // the right interfaces of its cells
-        const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
-        count_newton(st, valid, conv ? iters : 0, iters);
-        if (GUESS) count_flag(&st->fallbacks, valid && fb);
-        if (ex.log)
-          log_interface(ex, valid, qp, qm_next, pstar,
-                        ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
-                            ((unsigned long long)row * (d.nx + 1) + (i + 1)) * 2ull);
-      }
-
-      // WRITE: conservative update of cells x0 .. x0+59
+      // WRITE: cells x0 .. x0+59
       if (lane >= 2 && lane < 62 && i < d.nx) {
-        const T nr = u0 + lam * (Fl.m - F.m);
-        const T nn = un + lam * (Fl.n - F.n);
-        const T nt = ut + lam * (Fl.t - F.t);
-        const T ne = e + lam * (Fl.e - F.e);
-        outp[i] = nr;
-        outp[P + i] = nn;
-        outp[2 * P + i] = nt;
-        outp[3 * P + i] = ne;
-        if constexpr (NS > 0) outp[4 * P + i] = sx + lam * (FXl - FX);
-        status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
-        if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
+        outp[i] = c.r;
+        outp[P + i] = c.n;
+        outp[2 * P + i] = c.t;
+        outp[3 * P + i] = c.e;
+        if constexpr (NS > 0) outp[4 * P + i] = c.s;
+        status |= nonphysical(c.r, c.e) ? kStatusNonPhys : 0;
+        if constexpr (FUSE) smax = fmax(smax, max_speed(c.r, c.n, c.t, c.e, G));
       }
     }
     if (status) atomicOr(&st->status, status);
@@ -525,6 +560,140 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
   }
 }
 
+// ------------------------------------------------------------ tiled y-sweep
+// The y-sweep in the x-sweep's form, through a tile transposed in LDS (the
+// alternative to the column march above; option ysweep = tile).  A work item
+// is a block-wide tile: kTileCols columns by 64 rows (the 60 rows it updates
+// and two ghost rows on each side), read row-coalesced into LDS with the
+// boundary rule in the row index remap.  Each wave then takes every fourth
+// column of the tile as a 64-lane pencil segment (pencil_segment, one cell per
+// lane), writes the updated cells back into its own column of the tile, and
+// after a barrier the block stores the 60 rows row-coalesced.  Tile columns
+// are XOR-swizzled by row (tile_col) so that both the row-wise fill and the
+// column-wise lane reads hit distinct LDS banks.  Same numerics as the x-sweep
+// (the same device code), so results equal the march to rounding; per updated
+// cell it executes the 64/60 lanes of a segment and the shuffles of the x-sweep
+// instead of the march's register window.
+// LDS column of tile element (r, c): c XOR a function of the row, so that the
+// 16 lanes of a wave that the LDS serves together (a row-wise fill: one row
+// per 16 lanes; a column read: 16 consecutive rows) fall on distinct banks of
+// the 32 4-byte banks.  A row of 16 FP64 values spans all 32 banks, so
+// consecutive rows take different XOR keys; a row of 16 FP32 values spans
+// half of them, so pairs of rows share a key.
+template <typename T>
+__device__ __forceinline__ int tile_col(int r, int c) {
+  return c ^ ((sizeof(T) == 8 ? r : r >> 1) & (kTileCols - 1));
+}
+
+template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_y_tile(Batch<T> b, Gas<T> G, Extras ex) {
+  constexpr int NV = 4 + NS;
+  __shared__ T tile[NV][kTileRows][kTileCols];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+  int status = 0;
+  T smax = T(0);  // max wave speed of the written cells (FUSE), per grid
+  int gcur = -1;  // grid smax belongs to
+  for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
+    const int gi = find_grid<Key::Tile>(b.g, b.ngrids, it);
+    const GridDesc d = b.g[gi];
+    DevState* st = b.st + gi;
+    if (gi != gcur) {  // flush the previous grid's status and max speed
+      if (gcur >= 0) {
+        if (status) atomicOr(&b.st[gcur].status, status);
+        if constexpr (FUSE) {
+          const double wmax = wave_max((double)smax);
+          if (lane == 0) fold_max(&b.st[gcur].acc, wmax);
+        }
+      }
+      status = 0;
+      smax = T(0);
+      gcur = gi;
+    }
+    const int li = (int)(it - d.wt0);
+    const int ncols = (d.nx + kTileCols - 1) / kTileCols;
+    const int ty = li / ncols;
+    const int x0 = (li - ty * ncols) * kTileCols;
+    const int y0 = ty * kTileOut;
+    const T lam = T(st->dt / d.h);
+    const long long P = d.plane;
+    // READ: rows y0-2 .. y0+61 (ghost rows by index remap, rows past ny+1
+    // clamped), columns x0 .. x0+15 (past nx clamped); planes in pencil order
+    // (rho, normal rho v, transverse rho u, E, rho X)
+#pragma unroll
+    for (int k = 0; k < kTileRows * kTileCols / 256; ++k) {
+      const int e = tid + 256 * k;
+      const int r = e / kTileCols, cl = e % kTileCols;
+      bool flip;
+      const int src = ghost_source(min(y0 - 2 + r, d.ny + 1), d.ny, d.bc, flip);
+      const T* p = b.src + d.off + (long long)src * d.pitch + min(x0 + cl, d.nx - 1);
+      const int cc = tile_col<T>(r, cl);
+      const T vr = p[0], vu = p[P], vv = p[2 * P], ve = p[3 * P];
+      tile[0][r][cc] = vr;
+      tile[1][r][cc] = flip ? -vv : vv;
+      tile[2][r][cc] = vu;
+      tile[3][r][cc] = ve;
+      if constexpr (NS > 0) tile[4][r][cc] = p[4 * P];
+    }
+    __syncthreads();
+    // COMPUTE: wave wv takes columns wv, wv+4, ...; lane l is row y0-2+l
+    const int i = y0 - 2 + lane;
+    for (int cl = wv; cl < kTileCols && x0 + cl < d.nx; cl += kWavesPerBlock) {
+      const int cc = tile_col<T>(lane, cl);
+      Lane<T> c;
+      c.r = tile[0][lane][cc];
+      c.n = tile[1][lane][cc];
+      c.t = tile[2][lane][cc];
+      c.e = tile[3][lane][cc];
+      c.s = T(0);
+      if constexpr (NS > 0) c.s = tile[4][lane][cc];
+      // interfaces owned: y0-1/2 (first tile only) and the right interfaces
+      // of the updated rows
+      const bool valid = (lane >= 2 || (lane == 1 && y0 == 0)) && lane < 62 && i < d.ny;
+      const int x = x0 + cl;
+      pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
+          c, lam, G, ex, st, valid,
+          ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
+              (((unsigned long long)x * (d.ny + 1) + (i + 1)) * 2ull + 1ull));
+      if (lane >= 2 && lane < 62 && i < d.ny) {
+        tile[0][lane][cc] = c.r;
+        tile[1][lane][cc] = c.n;
+        tile[2][lane][cc] = c.t;
+        tile[3][lane][cc] = c.e;
+        if constexpr (NS > 0) tile[4][lane][cc] = c.s;
+        status |= nonphysical(c.r, c.e) ? kStatusNonPhys : 0;
+        if constexpr (FUSE) smax = fmax(smax, max_speed(c.r, c.n, c.t, c.e, G));
+      }
+    }
+    __syncthreads();
+    // WRITE: rows y0 .. y0+59 (below ny), columns x0 .. x0+15 (below nx)
+#pragma unroll
+    for (int k = 0; k < (kTileOut * kTileCols + 255) / 256; ++k) {
+      const int e = tid + 256 * k;
+      const int r = e / kTileCols, cl = e % kTileCols;
+      const int j = y0 + r, x = x0 + cl;
+      if (e < kTileOut * kTileCols && j < d.ny && x < d.nx) {
+        const int cc = tile_col<T>(r + 2, cl);
+        T* p = b.dst + d.off + (long long)j * d.pitch + x;
+        __builtin_nontemporal_store(tile[0][r + 2][cc], p);
+        __builtin_nontemporal_store(tile[2][r + 2][cc], p + P);
+        __builtin_nontemporal_store(tile[1][r + 2][cc], p + 2 * P);
+        __builtin_nontemporal_store(tile[3][r + 2][cc], p + 3 * P);
+        if constexpr (NS > 0) __builtin_nontemporal_store(tile[4][r + 2][cc], p + 4 * P);
+      }
+    }
+    __syncthreads();  // the next item refills the tile
+  }
+  if (gcur >= 0) {
+    if (status) atomicOr(&b.st[gcur].status, status);
+    if constexpr (FUSE) {
+      const double wmax = wave_max((double)smax);
+      if (lane == 0) fold_max(&b.st[gcur].acc, wmax);
+    }
+  }
+}
+
 // ------------------------------------------------------------ variant tables
 // Sweep kernel variants: instrumentation, learned guess, fused reduction,
 // limiter and interface solver are template arguments; index within one
@@ -546,8 +715,10 @@ constexpr SweepFn<T> sweep_variant() {
     return nullptr;
   else if constexpr (DIR == 0)
     return &k_sweep_x<T, I, GS, L, F, RS, NS>;
-  else
+  else if constexpr (DIR == 1)
     return &k_sweep_y<T, I, GS, L, F, RS, NS>;
+  else
+    return &k_sweep_y_tile<T, I, GS, L, F, RS, NS>;
 }
 
 template <typename T, int DIR, int NS, int... V>

@@ -48,20 +48,22 @@ def sample_columns(U):
     return sorted(set(int(c) for c in cols))
 
 
-@pytest.mark.parametrize("dtype_name,riemann,ns", [("f64", 0, 0), ("f32", 0, 0), ("f64", 1, 0),
-                                                   ("f64", 2, 0), ("f64", 0, 1)])
-def test_fullsize_step(torch_cuda_fs, orc, state, dtype_name, riemann, ns):
+@pytest.mark.parametrize("dtype_name,riemann,ns,ysweep", [
+    ("f64", 0, 0, 0), ("f32", 0, 0, 0), ("f64", 1, 0, 0), ("f64", 2, 0, 0), ("f64", 0, 1, 0),
+    ("f64", 0, 0, 1), ("f32", 0, 0, 1)])
+def test_fullsize_step(torch_cuda_fs, orc, state, dtype_name, riemann, ns, ysweep):
     torch = torch_cuda_fs
     from paper_2106_13465_amd.hydro import Hydro
 
     U = state
     if ns:
         U = inputs.with_scalars(U, inputs.random_scalars(N, N, seed=7, k=ns))
-    print(f"fullsize {dtype_name} solver {riemann} scalars {ns}: 8192^2 one step", flush=True)
+    print(f"fullsize {dtype_name} solver {riemann} scalars {ns} ysweep {ysweep}: 8192^2 one step",
+          flush=True)
     c = orc.cfg(bc=orc.BC_PERIODIC, riemann=riemann, nscalars=ns)
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     h = Hydro(N, N, 1.4, 0.8, "periodic", dtype=dtype, nscalars=ns)
-    h.set_options(riemann=riemann)
+    h.set_options(riemann=riemann, ysweep=ysweep)
     h.set_state(U)
     if riemann == 0 and ns == 0:
         h.autotune(use_cache=True)  # the launch shape bench.py times
