@@ -599,6 +599,82 @@ def _timed_steps(obj, steps, graph=False):
     return a.elapsed_time(b) / steps
 
 
+STRONG_FAMILIES = {"strong_jumps_p2": dict(p_decades=2.0, rho_decades=1.0, speed=2.0),
+                   "strong_jumps_p4": dict(p_decades=4.0, rho_decades=2.0, speed=3.0)}
+
+
+def strong_jump_study(fam, n=4096, reps=3) -> dict:
+    """The learned guess where the two-rarefaction guess is poor: a network
+    trained (20 epochs) on the interface states the solver logs in one step of
+    a 1024^2 grid of strong jumps of the family, then the first step of a fresh
+    n^2 grid of the family with the two-rarefaction guess, the gated learned
+    guess and the learned guess everywhere, FP64 and FP32: iterations, sweep
+    times (best of reps), and the time ratio to the two-rarefaction start."""
+    import torch
+
+    from paper_2106_13465_amd import inputs
+    from paper_2106_13465_amd.hydro import Hydro
+    from paper_2106_13465_amd._lib import HYDRO_LEARNED_GATE_DEFAULT as GATE_DEFAULT
+    from paper_2106_13465_amd.mlp import GuessNetwork
+
+    rec = torch.zeros((2_200_000, 8), dtype=torch.float32, device="cuda:0")
+    h = Hydro(1024, 1024, 1.4, 0.8, "periodic", dtype=torch.float64, device="cuda:0")
+    h.set_state(inputs.strong_jumps(1024, 1024, 31, **fam))
+    h.set_logger(rec, seed=7, rate_smooth=1.0, rate_strong=1.0)
+    h.step(1)
+    nrec = min(h.logger_count(), rec.shape[0])
+    h.set_logger(None)
+    h.close()
+    net_s = GuessNetwork(seed=0, device="cuda:0")
+    X, Y = net_s.features(rec[:nrec])
+    del rec
+    hist = net_s.train(X, Y, epochs=20, batch=2048, lr=2e-3, seed=1)
+    err = (net_s.forward(X) - Y).abs()[Y.abs() < 8].float()
+    sres = {"family": fam, "grid": f"{n}^2, periodic, first step of a fresh seed",
+            "training": {"records": nrec, "epochs": 20, "batch": 2048, "lr": 2e-3,
+                         "loss_first_last": [hist[0], hist[-1]],
+                         "median_abs_ln_error": float(err.median().item()),
+                         "p90_abs_ln_error": float(torch.quantile(err[:1_000_000], 0.9).item())}}
+    del X, Y, err
+    U4 = inputs.strong_jumps(n, n, 32, **fam)
+    for dn, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        for name, guess, gate in (("two_rarefaction", 0, 0.0), ("learned", 1, GATE_DEFAULT),
+                                  ("learned_everywhere", 1, 0.0)):
+            h = Hydro(n, n, 1.4, 0.8, "periodic", dtype=dt, device="cuda:0")
+            if guess:
+                h.set_mlp(net_s)
+            h.set_options(guess=guess, learned_gate=gate, stats=1)
+            h.set_state(U4)
+            h.step(1)
+            it = _iter_stats(h)
+            h.set_options(stats=0)
+            h.set_profiling(True)
+            xs, ys = [], []
+            for _ in range(reps):
+                h.set_state(U4)
+                h.profile(reset=True)
+                h.step(1)
+                pr = h.profile(reset=True)
+                xs.append(pr["sweep_x"]["ms"])
+                ys.append(pr["sweep_y"]["ms"])
+            h.close()
+            del h
+            sres[f"{dn}_{name}"] = {"newton": it, "sweep_x_ms": min(xs), "sweep_y_ms": min(ys)}
+        base = sres[f"{dn}_two_rarefaction"]
+        for name in ("learned", "learned_everywhere"):
+            r = sres[f"{dn}_{name}"]
+            r["iteration_ratio_vs_two_rarefaction"] = (
+                r["newton"]["mean_iterations"] / base["newton"]["mean_iterations"])
+            r["wave_max_iteration_ratio_vs_two_rarefaction"] = (
+                r["newton"]["wave_mean_max_iterations"]
+                / base["newton"]["wave_mean_max_iterations"])
+            r["sweep_time_ratio_vs_two_rarefaction"] = (
+                (r["sweep_x_ms"] + r["sweep_y_ms"]) / (base["sweep_x_ms"] + base["sweep_y_ms"]))
+    del U4
+    torch.cuda.empty_cache()
+    return sres
+
+
 def bench_learned(args) -> dict:
     """Learned Riemann guess: log interface states from the corner-blast and
     Fourier+blasts runs, train the network on the GPU, then compare it with the
@@ -629,7 +705,7 @@ def bench_learned(args) -> dict:
     h = Hydro(8192, 8192, 1.4, 0.8, "periodic", dtype=torch.float32, device="cuda:0")
     h.set_state(U2)
     del U2
-    h.set_logger(records[n1:], seed=12, rate_smooth=0.004, rate_strong=1.0)
+    h.set_logger(records[n1:], seed=12, rate_smooth=0.0065, rate_strong=1.0)
     h.step(12)
     n2 = min(h.logger_count(), cap - n1)
     h.set_logger(None)
@@ -740,61 +816,9 @@ def bench_learned(args) -> dict:
     out["quadrant_batch_64"] = qres
 
     # --- strong jumps: a network trained on logs of such grids, first step of a fresh grid
-    for fname, fam in (("strong_jumps_p2", dict(p_decades=2.0, rho_decades=1.0, speed=2.0)),
-                       ("strong_jumps_p4", dict(p_decades=4.0, rho_decades=2.0, speed=3.0))):
+    for fname, fam in STRONG_FAMILIES.items():
         print(f"# {fname}", file=sys.stderr, flush=True)
-        rec = torch.zeros((2_200_000, 8), dtype=torch.float32, device="cuda:0")
-        h = Hydro(1024, 1024, 1.4, 0.8, "periodic", dtype=torch.float64, device="cuda:0")
-        h.set_state(inputs.strong_jumps(1024, 1024, 31, **fam))
-        h.set_logger(rec, seed=7, rate_smooth=1.0, rate_strong=1.0)
-        h.step(1)
-        n = min(h.logger_count(), rec.shape[0])
-        h.set_logger(None)
-        h.close()
-        net_s = GuessNetwork(seed=0, device="cuda:0")
-        X, Y = net_s.features(rec[:n])
-        del rec
-        hist = net_s.train(X, Y, epochs=20, batch=2048, lr=2e-3, seed=1)
-        err = (net_s.forward(X) - Y).abs()[Y.abs() < 8].float()
-        sres = {"family": fam, "grid": "4096^2, periodic, first step of a fresh seed",
-                "training": {"records": n, "epochs": 20, "batch": 2048, "lr": 2e-3,
-                             "loss_first_last": [hist[0], hist[-1]],
-                             "median_abs_ln_error": float(err.median().item())}}
-        del X, Y, err
-        U4 = inputs.strong_jumps(4096, 4096, 32, **fam)
-        for dn, dt in (("f64", torch.float64), ("f32", torch.float32)):
-            for name, guess, gate in (("two_rarefaction", 0, 0.0), ("learned", 1, GATE_DEFAULT),
-                                      ("learned_everywhere", 1, 0.0)):
-                h = Hydro(4096, 4096, 1.4, 0.8, "periodic", dtype=dt, device="cuda:0")
-                if guess:
-                    h.set_mlp(net_s)
-                h.set_options(guess=guess, learned_gate=gate, stats=1)
-                h.set_state(U4)
-                h.step(1)
-                it = _iter_stats(h)
-                h.set_options(stats=0)
-                h.set_profiling(True)
-                xs, ys = [], []
-                for _ in range(3):
-                    h.set_state(U4)
-                    h.profile(reset=True)
-                    h.step(1)
-                    pr = h.profile(reset=True)
-                    xs.append(pr["sweep_x"]["ms"])
-                    ys.append(pr["sweep_y"]["ms"])
-                h.close()
-                del h
-                sres[f"{dn}_{name}"] = {"newton": it, "sweep_x_ms": min(xs), "sweep_y_ms": min(ys)}
-            base = sres[f"{dn}_two_rarefaction"]
-            for name in ("learned", "learned_everywhere"):
-                r = sres[f"{dn}_{name}"]
-                r["iteration_ratio_vs_two_rarefaction"] = (
-                    r["newton"]["mean_iterations"] / base["newton"]["mean_iterations"])
-                r["sweep_time_ratio_vs_two_rarefaction"] = (
-                    (r["sweep_x_ms"] + r["sweep_y_ms"]) / (base["sweep_x_ms"] + base["sweep_y_ms"]))
-        del U4
-        torch.cuda.empty_cache()
-        out[fname] = sres
+        out[fname] = strong_jump_study(fam)
     return out
 
 
@@ -808,7 +832,8 @@ def main() -> int:
                          "128 blast_corner)")
     ap.add_argument("--workload", default="fourier_blasts",
                     choices=["fourier_blasts", "fourier_smooth", "shear_layer", "blast_corner",
-                             "strong_jumps", "multiblast_batch", "quadrant_batch", "learned"])
+                             "strong_jumps", "multiblast_batch", "quadrant_batch", "learned",
+                             "learned_strong"])
     ap.add_argument("--train-records", type=int, default=10_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
@@ -845,6 +870,11 @@ def main() -> int:
 
     if args.workload == "learned":
         print(json.dumps(bench_learned(args)), flush=True)
+        return 0
+    if args.workload == "learned_strong":
+        # the strong-jump part of the learned-guess study alone (p over 4 decades)
+        print(json.dumps({"strong_jumps_p4": strong_jump_study(
+            STRONG_FAMILIES["strong_jumps_p4"], n=args.size or 4096)}), flush=True)
         return 0
 
     if args.workload == "strong_jumps":

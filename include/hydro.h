@@ -330,14 +330,15 @@ int hydro_get_profile(hydro_t *h, double ms[HYDRO_NPHASES], long long launches[H
  * Learned starting guess for the star pressure (an addition to the paper's
  * method; the two-rarefaction guess with the full Newton cap stays the
  * fallback).  A 6 -> 32 -> 32 -> 1 network with ReLU activations, BF16 weights
- * and activations on the MFMA units, FP32 accumulation.  Features of an
- * interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar), w = asinh((u_L-u_bar)/c_bar),
- * x = (a, b, w, -a, -b, -w) with geometric means rho_bar, p_bar, u_bar the
- * mean velocity and c_bar = sqrt(gamma p_bar/rho_bar); output
- * y ~ ln(p_star / p_bar).  In a sweep with options.guess = HYDRO_GUESS_MLP, Newton
- * runs at most 4 iterations from p_bar exp(y); if its convergence test fails
- * (or the guess is not a finite positive pressure) the interface restarts
- * from the two-rarefaction guess with the full cap and counts as a fallback.
+ * and activations on the MFMA units, FP32 accumulation.  It corrects the
+ * two-rarefaction guess p_ptr.  Features of an interface:
+ * a = ln(rho_L/rho_bar), b = ln(p_L/p_bar), w = asinh((u_L-u_bar)/c_bar),
+ * q = ln(p_ptr/p_bar), x = (a, b, w, q, -a, -b) with geometric means rho_bar,
+ * p_bar, u_bar the mean velocity and c_bar = sqrt(gamma p_bar/rho_bar);
+ * output y ~ ln(p_star / p_ptr).  In a sweep with options.guess =
+ * HYDRO_GUESS_MLP, Newton runs at most 4 iterations from p_ptr exp(y); if its
+ * convergence test fails (or the guess is not a finite positive pressure) the
+ * interface restarts from p_ptr with the full cap and counts as a fallback.
  *
  * Parameters: HYDRO_MLP_PARAMS FP32 values, flat and row-major:
  * W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3.  All pointers below are
@@ -351,7 +352,8 @@ size_t hydro_mlp_dev_bytes(void);
  * parameter is not finite: then every learned guess falls back). */
 int hydro_mlp_pack(const float *params, void *mlp, void *stream);
 /* Logged interface records [n][8] -> features X [n][6] and targets
- * Y [n] = ln(p_star / p_bar) (Y may be NULL). */
+ * Y [n] = ln(p_star / p_ptr) (Y may be NULL); p_ptr is the two-rarefaction
+ * guess of the record's states, in FP64. */
 int hydro_mlp_features(const float *records, long long n, double gamma, float *X, float *Y,
                        void *stream);
 /* Y[n] = network output for X [n][6]. */

@@ -15,13 +15,17 @@
  * for W1's gradient).  Everything else, including every sum, is FP64.
  *
  * Features of an interface: a = ln(rho_L/rho_bar), b = ln(p_L/p_bar),
- * w = asinh((u_L - u_bar)/c_bar), x = (a, b, w, -a, -b, -w),
- * target ln(p_star / p_bar),
- * with rho_bar, p_bar geometric means, u_bar the mean velocity and
- * c_bar = sqrt(gamma p_bar / rho_bar).
+ * w = asinh((u_L - u_bar)/c_bar), q = ln(p_ptr/p_bar),
+ * x = (a, b, w, q, -a, -b), target ln(p_star / p_ptr),
+ * with rho_bar, p_bar geometric means, u_bar the mean velocity,
+ * c_bar = sqrt(gamma p_bar / rho_bar) and p_ptr the two-rarefaction guess of
+ * the two states (oracle_ptr_guess): the network learns the correction to
+ * the method's own starting guess.
  */
 #include <math.h>
 #include <string.h>
+
+#include "hydro_oracle.h"
 
 #define NH 32
 #define NI 6
@@ -119,11 +123,14 @@ void mlp_oracle_features(const double *rec, double gamma, double *x, double *tar
   const double pbar = sqrt(rec[2] * rec[5]);
   const double ubar = 0.5 * (rec[1] + rec[4]);
   const double cbar = sqrt(gamma * pbar / rbar);
+  const double qL[4] = {rec[0], rec[1], 0.0, rec[2]};
+  const double qR[4] = {rec[3], rec[4], 0.0, rec[5]};
+  const double p_ptr = oracle_ptr_guess(qL, qR, gamma);
   x[0] = log(rec[0] / rbar);
   x[1] = log(rec[2] / pbar);
   x[2] = asinh((rec[1] - ubar) / cbar);
-  x[3] = log(rec[3] / rbar);
-  x[4] = log(rec[5] / pbar);
-  x[5] = asinh((rec[4] - ubar) / cbar);
-  if (target) *target = log(rec[6] / pbar);
+  x[3] = log(p_ptr / pbar);
+  x[4] = log(rec[3] / rbar);
+  x[5] = log(rec[5] / pbar);
+  if (target) *target = log(rec[6] / p_ptr);
 }

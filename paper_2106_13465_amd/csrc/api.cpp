@@ -547,7 +547,7 @@ int hydro_mlp_features(const float* records, long long n, double gamma, float* X
   if (!records || !X || n < 0) return fail(HYDRO_EINVAL, "bad arguments");
   if (!(gamma > 1.0)) return fail(HYDRO_EINVAL, "gamma %g", gamma);
   if (n == 0) return HYDRO_OK;
-  hipError_t e = hydro::launch_mlp_features(records, n, (float)gamma, X, Y, (hipStream_t)stream);
+  hipError_t e = hydro::launch_mlp_features(records, n, gamma, X, Y, (hipStream_t)stream);
   if (e != hipSuccess) return dev_fail(e, "hydro_mlp_features");
   return HYDRO_OK;
 }

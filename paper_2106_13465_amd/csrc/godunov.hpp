@@ -207,27 +207,78 @@ __device__ __forceinline__ Flux<T> hllc_flux(const Prim<T>& L, const Prim<T>& R,
   return F;
 }
 
+// Two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), num = cL + cR -
+// (gamma-1)/2 (uR - uL), evaluated as pL [num / (cL + cR (pR/pL)^-z)]^(1/z) (one
+// fractional power); a non-positive numerator (vacuum) gives the floor pmin;
+// ipL = 1/pL.  SERIES: (pR/pL)^(-z) from its binomial series in e = pR/pL - 1
+// when every active lane of the wave has |e| <= 2^-10 (smooth flow; a
+// wave-uniform branch), else the general power.
+template <typename T, bool SERIES = false>
+__device__ __forceinline__ T two_rarefaction_guess(const Prim<T>& L, const Prim<T>& R,
+                                                   const Gas<T>& G, T cL, T cR, T ipL, T pmin) {
+  T q;
+  const T num = cL + cR - G.half_gm1 * (R.u - L.u);
+  if (num > T(0)) {
+    const T x = R.p * ipL;
+    const T e = x - T(1);
+    T xz;
+    if (SERIES && __ballot(!(fabs(e) <= T(kSeriesEps))) == 0ull)
+      xz = fma(e, fma(e, fma(e, fma(e, G.ser[3], G.ser[2]), G.ser[1]), G.ser[0]), T(1));
+    else
+      xz = G.ipow_k > 0 ? fm::root_inv(x, G.ipow_k, G.z) : fm::pow_pos(x, -G.z);
+    const T den = cL + cR * xz;
+    const T ratio = num * fm::rcp(den);
+    q = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
+  } else {
+    q = pmin;
+  }
+  return fmax(q, pmin);
+}
+
+// The two-rarefaction guess of a pair of primitive states on its own (no
+// other part of the Riemann solve): sound speeds, floor and 1/pL from L, R.
+template <typename T>
+__device__ __forceinline__ T two_rarefaction_of(const Prim<T>& L, const Prim<T>& R,
+                                                const Gas<T>& G) {
+  const T cL = fm::sqrt(G.g * L.p * fm::rcp(L.r));
+  const T cR = fm::sqrt(G.g * R.p * fm::rcp(R.r));
+  const T pmin = fmin(L.r, R.r) * G.pfloor;
+  return two_rarefaction_guess<T>(L, R, G, cL, cR, fm::rcp(L.p), pmin);
+}
+
+// No learned starting guess (the plain method): the functor riemann_flux calls
+// with the two-rarefaction guess.
+struct NoLearnedGuess {
+  static constexpr bool enabled = false;
+  template <typename T>
+  __device__ T operator()(const Prim<T>&, const Prim<T>&, T) const {
+    return T(0);
+  }
+};
+
 // Riemann problem at one interface: left state L, right state R.  Returns the
 // flux of the Godunov state at x/t = 0.  RS: 0 the two-shock solver, 1 the
 // exact solver (Newton on the exact wave curves, exact sampling of the
 // self-similar solution, fans included), 2 the HLLC flux (no iteration:
-// iters = 0, converged, no learned guess).  p_learned > 0 is a learned starting
-// guess: Newton runs at most niter_learned iterations from it, and if the
-// convergence test has not been met the solve restarts from the
-// two-rarefaction guess with the full cap (fell_back).  p_learned < 0 means a
-// learned guess was produced but is unusable (also a fall-back); 0 means no
-// learned guess.  iters counts all iterations; pstar returns the final star
-// pressure; left says whether x/t = 0 lies left of the contact (the side
-// whose passive scalars cross the interface).  SERIES lets the two-rarefaction
-// guess take (p_R/p_L)^(-z) from its binomial series in smooth waves (the
-// same value to rounding, fewer instructions than the general power in FP64).
-template <int RS, typename T, bool SERIES = false>
+// iters = 0, converged, no learned guess).  Newton starts from the
+// two-rarefaction guess p_ptr, or, when learn is enabled, from the learned
+// guess learn(L, R, p_ptr) (called by every lane of the wave): > 0 a learned
+// start, from which Newton runs at most niter_learned iterations and, if the
+// convergence test has not been met, restarts from p_ptr with the full cap
+// (fell_back); < 0 a learned guess that is unusable (also a fall-back); 0 no
+// learned guess for this interface.  iters counts all iterations; pstar
+// returns the final star pressure; left says whether x/t = 0 lies left of the
+// contact (the side whose passive scalars cross the interface).  SERIES lets
+// the two-rarefaction guess take (p_R/p_L)^(-z) from its binomial series in
+// smooth waves (the same value to rounding, fewer instructions than the
+// general power in FP64).
+template <int RS, typename T, bool SERIES = false, typename Learn = NoLearnedGuess>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
-                                                const Gas<T>& G, T p_learned, int& iters,
+                                                const Gas<T>& G, const Learn& learn, int& iters,
                                                 bool& converged, bool& fell_back, T& pstar,
                                                 bool& left_out) {
   if constexpr (RS == 2) {
-    (void)p_learned;
+    (void)learn;
     iters = 0;
     converged = true;
     fell_back = false;
@@ -259,33 +310,17 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   const T aR = G.half_gm1 * R.p;
   const T pmin = fmin(L.r, R.r) * G.pfloor;
 
-  // two-rarefaction guess [num / (cL pL^-z + cR pR^-z)]^(1/z), evaluated as
-  // pL [num / (cL + cR (pR/pL)^-z)]^(1/z): one fractional power
-  auto two_rarefaction = [&]() -> T {
-    T q;
-    const T num = cL + cR - G.half_gm1 * (R.u - L.u);
-    if (num > T(0)) {
-      const T x = R.p * ipL;
-      // (p_R/p_L)^(-z).  SERIES: the binomial series in e = p_R/p_L - 1 when
-      // every active lane of the wave has |e| <= 2^-10 (smooth flow; a
-      // wave-uniform branch), else the general power
-      const T e = x - T(1);
-      T xz;
-      if (SERIES && __ballot(!(fabs(e) <= T(kSeriesEps))) == 0ull)
-        xz = fma(e, fma(e, fma(e, fma(e, G.ser[3], G.ser[2]), G.ser[1]), G.ser[0]), T(1));
-      else
-        xz = G.ipow_k > 0 ? fm::root_inv(x, G.ipow_k, G.z) : fm::pow_pos(x, -G.z);
-      const T den = cL + cR * xz;
-      const T ratio = num * fm::rcp(den);
-      q = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
-    } else {
-      q = pmin;
-    }
-    return fmax(q, pmin);
-  };
-
-  const bool learned = p_learned > T(0);
-  T p = learned ? fmax(p_learned, pmin) : two_rarefaction();
+  // starting point: the two-rarefaction guess, or the learned correction of it
+  T p, p_ptr = T(0), p_learned = T(0);
+  bool learned = false;
+  if constexpr (Learn::enabled) {
+    p_ptr = two_rarefaction_guess<T, SERIES>(L, R, G, cL, cR, ipL, pmin);
+    p_learned = learn(L, R, p_ptr);
+    learned = p_learned > T(0);
+    p = learned ? fmax(p_learned, pmin) : p_ptr;
+  } else {
+    p = two_rarefaction_guess<T, SERIES>(L, R, G, cL, cR, ipL, pmin);
+  }
   int kmax = learned ? G.niter_learned : G.niter;
 
   // exact solver: 1/(rho_K c_K) = (1/rho_K) / c_K
@@ -345,12 +380,14 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   bool conv = newton_step(p);
   while (!conv) {
     if (k >= kmax) {
-      if (learned && !fb) {  // the learned guess failed its residual test
-        fb = true;
-        p = two_rarefaction();
-        k = 0;
-        kmax = G.niter;
-        continue;
+      if constexpr (Learn::enabled) {
+        if (learned && !fb) {  // the learned guess failed its residual test
+          fb = true;
+          p = p_ptr;
+          k = 0;
+          kmax = G.niter;
+          continue;
+        }
       }
       break;
     }
@@ -360,7 +397,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   }
   iters = total;
   converged = conv;
-  fell_back = fb || p_learned < T(0);
+  fell_back = Learn::enabled && (fb || p_learned < T(0));
   pstar = p;
 
   T gr, gu, gp, to;

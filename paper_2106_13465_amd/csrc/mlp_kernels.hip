@@ -19,6 +19,7 @@
 #include "device_state.hpp"
 #include "mlp.hpp"
 #include "mlp_launch.hpp"
+#include "plan.hpp"
 
 namespace hydro {
 
@@ -56,18 +57,21 @@ __global__ void k_mlp_pack(const float* __restrict__ p, MlpDev* m) {
 }
 
 // records [n][8] (rho_L, u_L, p_L, rho_R, u_R, p_R, p*, strength) ->
-// features X [n][6] and targets Y [n] = ln(p* / p_bar)
-__global__ void k_mlp_features(const float* __restrict__ rec, long long n, float gamma, float* X,
+// features X [n][6] and targets Y [n] = ln(p* / p_ptr), with the
+// two-rarefaction guess p_ptr of the record's states in FP64 (the FP64
+// sweep's arithmetic)
+__global__ void k_mlp_features(const float* __restrict__ rec, long long n, Gas<double> G, float* X,
                                float* Y) {
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
        s += (long long)gridDim.x * blockDim.x) {
     const float* r = rec + s * kLogFields;
-    Prim<float> L{r[0], r[1], 0.f, r[2]}, R{r[3], r[4], 0.f, r[5]};
-    float x[6], lpbar;
-    mlp_features(L, R, gamma, x, lpbar);
+    const Prim<double> L{r[0], r[1], 0.0, r[2]}, R{r[3], r[4], 0.0, r[5]};
+    const double p_ptr = two_rarefaction_of(L, R, G);
+    float x[6];
+    mlp_features(L, R, p_ptr, (float)G.g, x);
 #pragma unroll
     for (int k = 0; k < 6; ++k) X[s * 6 + k] = x[k];
-    if (Y) Y[s] = logf(r[6]) - lpbar;
+    if (Y) Y[s] = (float)log((double)r[6] / p_ptr);
   }
 }
 
@@ -286,12 +290,13 @@ hipError_t launch_mlp_pack(const float* params, MlpDev* m, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_features(const float* rec, long long n, float gamma, float* X, float* Y,
+hipError_t launch_mlp_features(const float* rec, long long n, double gamma, float* X, float* Y,
                                hipStream_t s) {
   long long nb = (n + 255) / 256;
   if (nb > 8192) nb = 8192;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)nb), dim3(256), 0, s, rec, n, gamma, X, Y);
+  const Gas<double> G = make_gas<double>(gamma, default_options());
+  hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)nb), dim3(256), 0, s, rec, n, G, X, Y);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ int mlp_grad_blocks(long long n);
 size_t mlp_grad_scratch_floats(long long n);
 
 hipError_t launch_mlp_pack(const float* params, MlpDev* m, hipStream_t s);
-hipError_t launch_mlp_features(const float* rec, long long n, float gamma, float* X, float* Y,
+hipError_t launch_mlp_features(const float* rec, long long n, double gamma, float* X, float* Y,
                                hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDev* m, const float* X, float* Y, long long n,
                               hipStream_t s);

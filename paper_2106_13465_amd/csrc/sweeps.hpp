@@ -135,6 +135,22 @@ __device__ __forceinline__ bool nonphysical(T r, T e) {
   return !(r > T(0)) || !(fabs(e) < T(INFINITY));
 }
 
+// Flux at one interface with the starting guess the variant selects: the
+// network's correction of the two-rarefaction guess (GUESS; net is the
+// network staged in LDS) or that guess itself.  Called by all 64 lanes.
+template <int RS, bool SERIES, int GUESS, typename T>
+__device__ __forceinline__ Flux<T> interface_flux(const Prim<T>& L, const Prim<T>& R,
+                                                  const Gas<T>& G, const Extras& ex,
+                                                  const MlpInfer* net, int& iters, bool& conv,
+                                                  bool& fb, T& pstar, bool& left) {
+  if constexpr (GUESS != 0 && RS != 2)
+    return riemann_flux<RS, T, SERIES>(
+        L, R, G, LearnedGuess{net, ex.gamma, ex.gate_kappa, ex.gate_theta2}, iters, conv, fb,
+        pstar, left);
+  else
+    return riemann_flux<RS, T, SERIES>(L, R, G, NoLearnedGuess{}, iters, conv, fb, pstar, left);
+}
+
 // First work item of this wave and the stride between a wave's items; both
 // wave-uniform.
 __device__ __forceinline__ long long first_wave() {
@@ -170,25 +186,30 @@ __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) 
 // variant (1: no constraint).  Values above what the variant needs on its own
 // trade spills of loop-invariant values for occupancy.  Timed on MI355X over
 // an 8192^2 state: the FP64 y-sweep runs 1.47 -> 1.21 ms at 3 waves instead
-// of 2, the FP32 y-sweep 0.69 -> 0.62 ms at 6 instead of 5, the FP32 sweeps
-// with the learned guess 1.09 -> 0.92 ms (x, 6 waves) and 0.75 -> 0.67 ms
-// (y, 5); asking for more (FP64 x at 5, FP32 at 8) spills inside the Newton
-// loop and runs 1.3-2.5x slower.
+// of 2, the FP32 y-sweep 0.69 -> 0.62 ms at 6 instead of 5; asking for more
+// (FP32 at 8) spills inside the Newton loop and runs 1.3-2.5x slower.  The
+// sweeps with the learned guess hold the network's tile in registers next to
+// their own state: 4 (FP64 x), 3 (FP64 y) and 5 (FP32) waves fit without
+// spilling (FP32 y: 3 registers).
 #ifndef HYDRO_OCC
-#define HYDRO_OCC 1, 1, 1, 6, 3, 1, 6, 5
+#define HYDRO_OCC 1, 4, 1, 5, 3, 3, 6, 5
 #endif
 constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 learned, then y
 // The exact solver's FP64 y-sweep needs more registers than 3 waves leave
 // (it spilled ~150 bytes per lane there); it asks for 2.  The HLLC FP32
 // y-sweep spilled 68 bytes at 6, the FP32 sweeps with a passive scalar 40-50;
 // they ask for 5.
-template <typename T, int GUESS, int RS, int NS>
+// The plain FP64 x-sweep (two-shock or HLLC, no scalar) is held at 5 waves:
+// 92 registers, no spill; left free, the allocator takes 98 and 4 waves.  With
+// the statistics or the fused max speed it spills at 5 and asks for 4.
+template <typename T, int GUESS, int RS, int NS, bool INSTR = false, bool FUSE = false>
 struct SweepOcc {
   static constexpr bool f32 = sizeof(T) == 4;
   static constexpr int v = (f32 ? 2 : 0) + (GUESS ? 1 : 0);
   static constexpr int cap_x = f32 && NS > 0 ? 5 : 8;
   static constexpr int cap_y = RS == 1 && !f32 ? 2 : f32 && (RS == 2 || NS > 0) ? 5 : 8;
-  static constexpr int x = kOcc[v] < cap_x ? kOcc[v] : cap_x;
+  static constexpr bool plain64 = !f32 && GUESS == 0 && RS != 1 && NS == 0;
+  static constexpr int x = plain64 ? (INSTR || FUSE ? 4 : 5) : (kOcc[v] < cap_x ? kOcc[v] : cap_x);
   static constexpr int y = kOcc[4 + v] < cap_y ? kOcc[4 + v] : cap_y;
   // tiled y-sweep (the x-sweep's code plus the tile loop): the FP64 default
   // variant at 4 waves (5 spilled; the two ran within 0.4% of each other in
@@ -217,7 +238,8 @@ struct Lane {
 // transposed through LDS.
 template <typename T, bool INSTR, int GUESS, int LIM, int RS, int NS>
 __device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& G,
-                                               const Extras& ex, DevState* st, bool iface_valid,
+                                               const Extras& ex, const MlpInfer* net,
+                                               DevState* st, bool iface_valid,
                                                unsigned long long log_key) {
   // COMPUTE: primitive variables, slopes, half-step face states
   T ir;
@@ -244,16 +266,13 @@ __device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& 
 
   // Riemann problem at this lane's right interface
   const Prim<T> qm_next = from_right(qm);
-  T p_learned = T(0);
-  if (GUESS)
-    p_learned = learned_guess<T>(ex.mlp, qp, qm_next, ex.gamma, ex.gate_kappa, ex.gate_theta2);
   int iters;
   bool conv, fb, left;
   T pstar;
   // FP64: the series form of the guess's power in smooth waves (measured
   // 4% faster on the x-sweep; no gain in FP32 or in the y-sweep's loop)
-  const Flux<T> F = riemann_flux<RS, T, sizeof(T) == 8>(qp, qm_next, G, p_learned, iters, conv,
-                                                        fb, pstar, left);
+  const Flux<T> F = interface_flux<RS, sizeof(T) == 8, GUESS>(qp, qm_next, G, ex, net, iters,
+                                                              conv, fb, pstar, left);
   const Flux<T> Fl = from_left(F);  // the lane's left interface
   // scalar flux: mass flux times X on the side of the contact at x/t = 0
   T FX = T(0), FXl = T(0);
@@ -278,8 +297,15 @@ __device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& 
 }
 
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
-__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
+__global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
+  // the learned guess's network, staged in LDS once per block
+  __shared__ MlpInfer net_lds;
+  const MlpInfer* net = nullptr;
+  if constexpr (GUESS != 0) {
+    mlp_stage(ex.mlp, &net_lds);
+    net = &net_lds;
+  }
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -317,7 +343,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::x)) void k_sweep_
       // the right interfaces of its cells
       const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
       pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
-          c, lam, G, ex, st, valid,
+          c, lam, G, ex, net, st, valid,
           ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
               ((unsigned long long)row * (d.nx + 1) + (i + 1)) * 2ull);
 
@@ -359,6 +385,13 @@ __device__ __forceinline__ Prim<T> slopes(const Prim<T>& a, const Prim<T>& b, co
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_y(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
+  // the learned guess's network, staged in LDS once per block
+  __shared__ MlpInfer net_lds;
+  const MlpInfer* net = nullptr;
+  if constexpr (GUESS != 0) {
+    mlp_stage(ex.mlp, &net_lds);
+    net = &net_lds;
+  }
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
     const GridDesc d = b.g[gi];
@@ -419,13 +452,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
         // rows outside -2 .. ny+1 are never used (the clamp keeps reads in range)
         const Cell<T> cn = load(max(min(j + 3, d.ny + 1), -2));
         if (j >= y0 - 1 && j < y1) {
-          T p_learned = T(0);
-          if (GUESS)
-            p_learned = learned_guess<T>(ex.mlp, qpA, qmB, ex.gamma, ex.gate_kappa, ex.gate_theta2);
           int iters;
           bool conv, fb, left;
           T pstar;
-          F = riemann_flux<RS>(qpA, qmB, G, p_learned, iters, conv, fb, pstar, left);
+          F = interface_flux<RS, false, GUESS>(qpA, qmB, G, ex, net, iters, conv, fb, pstar, left);
           if (INSTR) {
             const bool valid = xin && (j >= y0 || y0 == 0);
             count_newton(st, valid, conv ? iters : 0, iters);
@@ -507,13 +537,10 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
           }
         }
         if (j >= y0 - 1) {
-          T p_learned = T(0);
-          if (GUESS)
-            p_learned = learned_guess<T>(ex.mlp, qp0, qm1, ex.gamma, ex.gate_kappa, ex.gate_theta2);
           int iters;
           bool conv, fb, left;
           T pstar;
-          F = riemann_flux<RS>(qp0, qm1, G, p_learned, iters, conv, fb, pstar, left);
+          F = interface_flux<RS, false, GUESS>(qp0, qm1, G, ex, net, iters, conv, fb, pstar, left);
           if constexpr (NS > 0) FX = F.m * (left ? xp0 : xm1);
           if (INSTR) {
             const bool valid = xin && (j >= y0 || y0 == 0);
@@ -590,6 +617,14 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_
   constexpr int NV = 4 + NS;
   __shared__ T tile[NV][kTileRows][kTileCols];
   const int tid = threadIdx.x;
+  // the learned guess's network, staged in LDS once per block
+  __shared__ MlpInfer net_lds;
+  const MlpInfer* net = nullptr;
+  if constexpr (GUESS != 0) {
+    mlp_stage(ex.mlp, &net_lds);
+    net = &net_lds;
+  }
+
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
   int status = 0;
@@ -653,7 +688,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_
       const bool valid = (lane >= 2 || (lane == 1 && y0 == 0)) && lane < 62 && i < d.ny;
       const int x = x0 + cl;
       pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
-          c, lam, G, ex, st, valid,
+          c, lam, G, ex, net, st, valid,
           ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
               (((unsigned long long)x * (d.ny + 1) + (i + 1)) * 2ull + 1ull));
       if (lane >= 2 && lane < 62 && i < d.ny) {

@@ -23,11 +23,11 @@ OFF_W1, OFF_B1 = 0, 192
 OFF_W2, OFF_B2 = 224, 1248
 OFF_W3, OFF_B3 = 1280, 1312
 LOG_FIELDS = 8
-# Training targets ln(p*/p_bar) are clipped to +-TARGET_CLIP: near-vacuum
-# interfaces (p* at the pressure floor, ln ratios down to about -60) would
-# otherwise dominate the squared error; the guess only has to point Newton
-# the right way there, and the residual test hands such interfaces to the
-# two-rarefaction fallback.
+# Training targets ln(p*/p_ptr) (the correction of the two-rarefaction guess
+# p_ptr) are clipped to +-TARGET_CLIP: near-vacuum interfaces (p* at the
+# pressure floor, ln ratios down to about -60) would otherwise dominate the
+# squared error; the guess only has to point Newton the right way there, and
+# the residual test hands such interfaces to the two-rarefaction fallback.
 TARGET_CLIP = 8.0
 
 
@@ -85,7 +85,8 @@ class GuessNetwork:
         self.pack()
 
     def features(self, records: torch.Tensor, gamma: float = 1.4):
-        """records float32 [n, 8] on the device -> (X [n, 6], Y [n])."""
+        """records float32 [n, 8] on the device -> (X [n, 6], Y [n]): features
+        (a, b, w, q, -a, -b) and targets ln(p*/p_ptr)."""
         n = records.shape[0]
         X = torch.empty((n, N_IN), dtype=torch.float32, device=self.device)
         Y = torch.empty(n, dtype=torch.float32, device=self.device)

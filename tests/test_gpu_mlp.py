@@ -213,12 +213,12 @@ def test_learned_guess_gains_on_strong_jumps(torch_cuda, orc):
     """What the trained network gains over the method without it, on grids of
     strong jumps (pressure over two decades, density over one, velocities up
     to twice the sound speed) with a network trained on interface states the
-    solver logged from such a grid: the same state, and the slow tail of the
-    two-rarefaction start (interfaces needing 5 or more Newton iterations,
-    which hold their whole wave) is cut to the fallbacks.  The mean count
-    barely moves: BF16 inputs bound the guess's accuracy to about 1e-2 in
-    ln p*, so most interfaces still need 3 or 4 steps, as from the
-    two-rarefaction guess."""
+    solver logged from such a grid to correct the two-rarefaction guess: the
+    same state, and the slow tail of the two-rarefaction start (interfaces
+    needing 5 or more Newton iterations, which hold their whole wave) is cut to
+    the fallbacks.  The mean count barely moves: BF16 inputs bound the guess's
+    accuracy to about 1e-2 in ln p*, so most interfaces still need 3 or 4
+    steps, as from the two-rarefaction guess."""
     from paper_2106_13465_amd.hydro import Hydro
     from paper_2106_13465_amd.mlp import GuessNetwork
 

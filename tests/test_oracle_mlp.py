@@ -63,10 +63,42 @@ def test_features_invariances(orc):
                                    b * pR, b * ps])
         np.testing.assert_allclose(x2, x, atol=1e-12)
         assert abs(t2 - t) < 1e-12
-        np.testing.assert_allclose(x[3:], -x[:3], atol=1e-15)
+        # the right state's slots are the left state's negated
+        np.testing.assert_allclose(x[4:], -x[:2], atol=1e-15)
+        # mirror image (left and right swapped, velocities negated): the same
+        # problem reflected, so a, b change sign and w, q and the target stay
+        xm, tm = orc.mlp_features([rR, -uR, pR, rL, -uL, pL, ps])
+        np.testing.assert_allclose(xm, [-x[0], -x[1], x[2], x[3], -x[4], -x[5]], atol=1e-12)
+        assert abs(tm - t) < 1e-12
+    # identical states: every feature is 0, and the two-rarefaction guess is
+    # the state's own pressure
     x, t = orc.mlp_features([1.3, 0.2, 0.7, 1.3, 0.2, 0.7, 0.7])
     np.testing.assert_allclose(x, 0, atol=1e-15)
     assert abs(t) < 1e-15
+
+
+def test_feature_q_is_the_exact_star_pressure_of_two_rarefactions(orc):
+    """q = ln(p_ptr / p_bar) with p_ptr the two-rarefaction guess: where both
+    waves are rarefactions that guess is the exact star pressure, so q equals
+    ln(p*/p_bar) of the independent bracketing solver (tests/exact_riemann.py);
+    the target is the log of the record's p* over that guess."""
+    import exact_riemann as ex
+
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 0
+    while n < 200:
+        rL, rR, pL, pR = np.exp(rng.uniform(-1.5, 1.5, 4))
+        cL, cR = np.sqrt(1.4 * pL / rL), np.sqrt(1.4 * pR / rR)
+        uL = rng.uniform(-0.5, 0.5)
+        uR = uL + rng.uniform(0.0, 1.5) * (cL + cR)  # separating: two rarefactions
+        ps, _ = ex.star((rL, uL, pL), (rR, uR, pR))
+        if not (ps < min(pL, pR)) or ps < 1e-6 * max(pL, pR):
+            continue
+        x, t = orc.mlp_features([rL, uL, pL, rR, uR, pR, 2.0 * ps])
+        pbar = np.sqrt(pL * pR)
+        assert abs(x[3] - np.log(ps / pbar)) < 1e-11
+        assert abs(t - np.log(2.0)) < 1e-11
+        n += 1
 
 
 def test_emulated_forward_close_to_exact(orc):
