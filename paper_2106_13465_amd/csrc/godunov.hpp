@@ -426,7 +426,7 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     T irs = iro + (po - p) * (iWo * iWo);
     irs = fmin(irs, G.inv_rho_min);
     const T rs = fm::rcp(irs);
-    const T cs = fmax(G.c_min, fm::sqrt(G.g * p * irs));
+    const T c2 = G.g * p * irs;  // c*^2 (the star sound speed is max(c_min, sqrt))
 
     // outer/inner edge speeds of the wave on that side, positive away from
     // the interface (s = +1 on the left, -1 on the right): a shock moves at
@@ -436,7 +436,12 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     const T wsh = Xo * iWo * iro - uos;
     const bool shock = p >= po;
     const T sout = shock ? wsh : co - uos;
-    const T sin_ = shock ? wsh : cs - uss;
+    // inner edge ahead of x/t = 0: for a rarefaction c* - s u* > 0, decided on
+    // squares (c* > s u* unless s u* >= c_min and c*^2 <= (s u*)^2); the
+    // square root is only taken inside a fan, where the interpolation needs
+    // c* (the sampled state is continuous where the two forms of the test
+    // could round differently)
+    const bool inner_ahead = shock ? wsh > T(0) : (uss < G.c_min || c2 > uss * uss);
 
     // x/t = 0 lies outside the wave (unperturbed side), inside the star
     // region, or inside a rarefaction fan (linear across it)
@@ -444,7 +449,8 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     gr = outside ? ro : rs;
     gu = outside ? uo : us;
     gp = outside ? po : p;
-    if (!outside && !(sin_ > T(0))) {
+    if (!outside && !inner_ahead) {
+      const T sin_ = shock ? wsh : fmax(G.c_min, fm::sqrt(c2)) - uss;
       T f = sout * fm::rcp(fmax(sout - sin_, G.c_min));
       f = fmin(fmax(f, T(0)), T(1));
       gr = f * rs + (T(1) - f) * ro;
