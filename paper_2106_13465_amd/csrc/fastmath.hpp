@@ -47,9 +47,23 @@ __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x
 __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float exp2(float y) { return __builtin_amdgcn_exp2f(y); }
 
-// x^k for a small positive integer k (uniform across the wave)
+// x^k for a small positive integer k (uniform across the wave).  The
+// exponents of the usual ratios of specific heats (3, 5, 7: gamma = 5/3, 7/5)
+// take a fixed chain of multiplications behind a scalar branch on k; any other
+// k the binary method, whose loop and selects cost three times as many vector
+// instructions.  Both multiply the same factors in the same order (x x^2 x^4
+// for k = 7), so the result does not depend on the path.
 template <typename T>
 __device__ __forceinline__ T ipow(T x, int k) {
+  if (k == 7) {
+    const T x2 = x * x;
+    return (x * x2) * (x2 * x2);
+  }
+  if (k == 5) {
+    const T x2 = x * x;
+    return x * (x2 * x2);
+  }
+  if (k == 3) return x * (x * x);
   T r = T(1);
   T b = x;
   while (k > 0) {

@@ -28,9 +28,11 @@ struct Gas {
   T half_gm1;  // (gamma - 1) / 2
   T h_coef;    // gamma / (gamma - 1): enthalpy factor of the energy flux
   T pfloor;    // c_min^2 / gamma: pressure floor per unit density
-  T rho_min;
-  T inv_rho_min;
-  T c_min;
+  // floors, fixed: as compile-time constants they enter instructions as
+  // literals and need no canonicalisation before a min / max
+  static constexpr T rho_min = T(kRhoMin);
+  static constexpr T inv_rho_min = T(1.0 / kRhoMin);
+  static constexpr T c_min = T(kCMin);
   T tol;       // Newton convergence test |dp| <= tol * p
   int niter;   // Newton iteration cap
   int niter_learned;  // cap from a learned guess before falling back

@@ -24,9 +24,6 @@ Gas<T> make_gas(double g, const hydro_options_t& o) {
   G.half_gm1 = T(0.5 * (g - 1.0));
   G.h_coef = T(g / (g - 1.0));
   G.pfloor = T(kCMin * kCMin / g);
-  G.rho_min = T(kRhoMin);
-  G.inv_rho_min = T(1.0 / kRhoMin);
-  G.c_min = T(kCMin);
   // Convergence can only be detected above the arithmetic's rounding noise:
   // in FP32 the test is floored at 8 ulp of 1.
   const double tol_floor = sizeof(T) == 4 ? 8.0 * 1.1920928955078125e-07 : 0.0;
