@@ -151,6 +151,30 @@ __device__ __forceinline__ Flux<T> interface_flux(const Prim<T>& L, const Prim<T
     return riemann_flux<RS, T, SERIES>(L, R, G, NoLearnedGuess{}, iters, conv, fb, pstar, left);
 }
 
+// A wave-uniform pointer moved to scalar registers (both halves read from the
+// first active lane) as a global-memory pointer, so that per-lane accesses
+// p + offset take the scalar-base form of the global load and store: a 32-bit
+// per-lane byte offset and no 64-bit address arithmetic per lane and access.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (global_ptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+// The element at byte offset boff (a non-negative in-range offset that fits
+// 32 bits) from base.
+template <typename T>
+__device__ __forceinline__ T at(global_ptr<const T> base, unsigned boff) {
+  return *(global_ptr<const T>)((global_ptr<const char>)base + boff);
+}
+template <typename T>
+__device__ __forceinline__ global_ptr<T> ptr_at(global_ptr<T> base, unsigned boff) {
+  return (global_ptr<T>)((global_ptr<char>)base + boff);
+}
+
 // First work item of this wave and the stride between a wave's items; both
 // wave-uniform.
 __device__ __forceinline__ long long first_wave() {
@@ -168,12 +192,27 @@ template <Key K>
 __device__ __forceinline__ long long key_of(const GridDesc& d) {
   return K == Key::X ? d.wx0 : (K == Key::Y ? d.wy0 : (K == Key::Tile ? d.wt0 : d.r0));
 }
+// Descriptor i of a batch's table.  The table is read-only while a kernel
+// runs and read at wave-uniform indices, so it is read through the constant
+// address space: scalar loads into scalar registers, which keeps the
+// arithmetic on its fields (rows, segments, plane pointers) scalar.
+__device__ __forceinline__ GridDesc load_desc(const GridDesc* g, int i) {
+  static_assert(sizeof(GridDesc) % 8 == 0, "descriptor read as 64-bit words");
+  typedef const __attribute__((address_space(4))) unsigned long long* const_words;
+  const const_words src = (const_words)(g + i);
+  unsigned long long w[sizeof(GridDesc) / 8];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(GridDesc) / 8); ++k) w[k] = src[k];
+  GridDesc d;
+  __builtin_memcpy(&d, w, sizeof(GridDesc));
+  return d;
+}
 template <Key K>
 __device__ __forceinline__ int find_grid(const GridDesc* g, int n, long long w) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (key_of<K>(g[mid]) <= w)
+    if (key_of<K>(load_desc(g, mid)) <= w)
       lo = mid;
     else
       hi = mid - 1;
@@ -308,7 +347,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
   }
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
-    const GridDesc d = b.g[gi];
+    const GridDesc d = load_desc(b.g, gi);
     DevState* st = b.st + gi;
     const int lw = (int)(w - d.wx0);
     const int nseg = (d.nx + kXOut - 1) / kXOut;
@@ -316,9 +355,14 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
     const int row = lw / chunks;
     const int seg0 = (lw - row * chunks) * b.seg;
     const T lam = T(st->dt / d.h);
+    const long long P = d.plane;
+    // the row's variable planes in scalar registers
     const T* rowp = b.src + d.off + (long long)row * d.pitch;
     T* outp = b.dst + d.off + (long long)row * d.pitch;
-    const long long P = d.plane;
+    const auto in0 = uniform_ptr(rowp), in1 = uniform_ptr(rowp + P);
+    const auto in2 = uniform_ptr(rowp + 2 * P), in3 = uniform_ptr(rowp + 3 * P);
+    const auto out0 = uniform_ptr(outp), out1 = uniform_ptr(outp + P);
+    const auto out2 = uniform_ptr(outp + 2 * P), out3 = uniform_ptr(outp + 3 * P);
     int status = 0;
     T smax = T(0);  // max wave speed of the written cells (FUSE)
 
@@ -330,11 +374,12 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
       // READ, with the boundary rule in the index remap
       bool flip;
       const int src = ghost_source(min(i, d.nx + 1), d.nx, d.bc, flip);
+      const unsigned so = (unsigned)src * (unsigned)sizeof(T);
       Lane<T> c;
-      c.r = rowp[src];
-      c.n = rowp[P + src];
-      c.t = rowp[2 * P + src];
-      c.e = rowp[3 * P + src];
+      c.r = at(in0, so);
+      c.n = at(in1, so);
+      c.t = at(in2, so);
+      c.e = at(in3, so);
       c.s = T(0);
       if constexpr (NS > 0) c.s = rowp[4 * P + src];
       if (flip) c.n = -c.n;
@@ -349,10 +394,11 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
 
       // WRITE: cells x0 .. x0+59
       if (lane >= 2 && lane < 62 && i < d.nx) {
-        outp[i] = c.r;
-        outp[P + i] = c.n;
-        outp[2 * P + i] = c.t;
-        outp[3 * P + i] = c.e;
+        const unsigned oo = (unsigned)i * (unsigned)sizeof(T);
+        *ptr_at(out0, oo) = c.r;
+        *ptr_at(out1, oo) = c.n;
+        *ptr_at(out2, oo) = c.t;
+        *ptr_at(out3, oo) = c.e;
         if constexpr (NS > 0) outp[4 * P + i] = c.s;
         status |= nonphysical(c.r, c.e) ? kStatusNonPhys : 0;
         if constexpr (FUSE) smax = fmax(smax, max_speed(c.r, c.n, c.t, c.e, G));
@@ -394,7 +440,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
   }
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::Y>(b.g, b.ngrids, w);
-    const GridDesc d = b.g[gi];
+    const GridDesc d = load_desc(b.g, gi);
     DevState* st = b.st + gi;
     const int lw = (int)(w - d.wy0);
     const int ncolg = (d.nx + kWave - 1) / kWave;
@@ -408,15 +454,24 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
     const int y0 = sg * b.seg;
     const int y1 = min(y0 + b.seg, d.ny);
     const T lam = T(st->dt / d.h);
+    // the grid's variable planes in scalar registers, rows added to them as
+    // scalar offsets, the lane's column as one 32-bit byte offset
+    const auto in0 = uniform_ptr(b.src + d.off), in1 = uniform_ptr(b.src + d.off + P);
+    const auto in2 = uniform_ptr(b.src + d.off + 2 * P), in3 = uniform_ptr(b.src + d.off + 3 * P);
+    const auto out0 = uniform_ptr(b.dst + d.off), out1 = uniform_ptr(b.dst + d.off + P);
+    const auto out2 = uniform_ptr(b.dst + d.off + 2 * P), out3 = uniform_ptr(b.dst + d.off + 3 * P);
+    const long long pitch = d.pitch;
+    const unsigned xo_in = (unsigned)(xin ? x : d.nx - 1) * (unsigned)sizeof(T);
+    const unsigned xo_out = (unsigned)x * (unsigned)sizeof(T);
 
     auto load = [&](int j) {
       bool flip;
-      const long long off = (long long)ghost_source(j, d.ny, d.bc, flip) * d.pitch;
+      const long long off = (long long)ghost_source(j, d.ny, d.bc, flip) * pitch;
       Cell<T> c;
-      c.r = col[off];
-      c.t = col[P + off];      // rho u: transverse
-      c.n = col[2 * P + off];  // rho v: normal
-      c.e = col[3 * P + off];
+      c.r = at(in0 + off, xo_in);
+      c.t = at(in1 + off, xo_in);  // rho u: transverse
+      c.n = at(in2 + off, xo_in);  // rho v: normal
+      c.e = at(in3 + off, xo_in);
       if (flip) c.n = -c.n;
       return c;
     };
@@ -472,11 +527,11 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
           const T nt = c0.t + lam * (Fm.t - F.t);
           const T ne = c0.e + lam * (Fm.e - F.e);
           if (xin) {
-            const long long off = (long long)j * d.pitch;
-            __builtin_nontemporal_store(nr, out + off);
-            __builtin_nontemporal_store(nt, out + P + off);
-            __builtin_nontemporal_store(nn, out + 2 * P + off);
-            __builtin_nontemporal_store(ne, out + 3 * P + off);
+            const long long off = (long long)j * pitch;
+            __builtin_nontemporal_store(nr, ptr_at(out0 + off, xo_out));
+            __builtin_nontemporal_store(nt, ptr_at(out1 + off, xo_out));
+            __builtin_nontemporal_store(nn, ptr_at(out2 + off, xo_out));
+            __builtin_nontemporal_store(ne, ptr_at(out3 + off, xo_out));
             status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
             if constexpr (FUSE) smax = fmax(smax, max_speed(nr, nn, nt, ne, G));
           }
@@ -558,13 +613,13 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
           const T nt = c0.t + lam * (Fm.t - F.t);
           const T ne = c0.e + lam * (Fm.e - F.e);
           if (xin) {
-            const long long off = (long long)j * d.pitch;
+            const long long off = (long long)j * pitch;
             // streaming stores: the next sweep reads these only after the
             // whole grid (measured faster for the y-sweep, slower for the x-sweep)
-            __builtin_nontemporal_store(nr, out + off);
-            __builtin_nontemporal_store(nt, out + P + off);
-            __builtin_nontemporal_store(nn, out + 2 * P + off);
-            __builtin_nontemporal_store(ne, out + 3 * P + off);
+            __builtin_nontemporal_store(nr, ptr_at(out0 + off, xo_out));
+            __builtin_nontemporal_store(nt, ptr_at(out1 + off, xo_out));
+            __builtin_nontemporal_store(nn, ptr_at(out2 + off, xo_out));
+            __builtin_nontemporal_store(ne, ptr_at(out3 + off, xo_out));
             if constexpr (NS > 0)
               __builtin_nontemporal_store(s0 + lam * (FmX - FX), out + 4 * P + off);
             status |= nonphysical(nr, ne) ? kStatusNonPhys : 0;
@@ -632,7 +687,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_
   int gcur = -1;  // grid smax belongs to
   for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
     const int gi = find_grid<Key::Tile>(b.g, b.ngrids, it);
-    const GridDesc d = b.g[gi];
+    const GridDesc d = load_desc(b.g, gi);
     DevState* st = b.st + gi;
     if (gi != gcur) {  // flush the previous grid's status and max speed
       if (gcur >= 0) {
