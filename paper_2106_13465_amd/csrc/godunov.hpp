@@ -273,8 +273,11 @@ struct NoLearnedGuess {
 // contact (the side whose passive scalars cross the interface).  SERIES lets
 // the two-rarefaction guess take (p_R/p_L)^(-z) from its binomial series in
 // smooth waves (the same value to rounding, fewer instructions than the
-// general power in FP64).
-template <int RS, typename T, bool SERIES = false, typename Learn = NoLearnedGuess>
+// general power in FP64).  CARRY (FP32 only): the final star velocity and
+// wave speeds from the last Newton iterate instead of a second evaluation of
+// both sides (fewer instructions, more registers live across the loop).
+template <int RS, typename T, bool SERIES = false, bool CARRY = false,
+          typename Learn = NoLearnedGuess>
 __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>& R,
                                                 const Gas<T>& G, const Learn& learn, int& iters,
                                                 bool& converged, bool& fell_back, T& pstar,
@@ -332,6 +335,9 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     izR = irR * fm::rcp(cR);
   }
 
+  // FP32, two-shock, CARRY: the last Newton step's W_K^2, 1/W_K, u*_L + u*_R
+  // and d(u*_R - u*_L)/dp at its pressure p_k, and the step p - p_k it took
+  T kXL = T(0), kXR = T(0), kiWL = T(0), kiWR = T(0), kus = T(0), kdus = T(0), kstep = T(0);
   // one Newton iteration on p; true when converged
   auto newton_step = [&](T& pp) -> bool {
     T dp;
@@ -358,6 +364,14 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
       if constexpr (sizeof(T) == 4)
         at_noise = fabs(usL - usR) <=
                    G.noise * ((fabs(L.u) + fabs(R.u)) + (fabs(dL) + fabs(dR)));
+      if constexpr (sizeof(T) == 4 && CARRY) {
+        kXL = XL;
+        kXR = XR;
+        kiWL = iWL;
+        kiWR = iWR;
+        kus = usL + usR;
+        kdus = izR2 - izL2;
+      }
     } else {
       // exact f(p) = f_L(p) + f_R(p) + u_R - u_L
       const T ip = fm::rcp(pp);
@@ -372,7 +386,9 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
     // a step from the floor that points below it: the root lies under the
     // floor (f increasing), so the floored star pressure is the floor
     const bool below_floor = pp == pmin && pp + dp < pmin;
+    const T p_k = pp;
     pp = fmax(pp + dp, pmin);
+    if constexpr (sizeof(T) == 4 && CARRY && RS == 0) kstep = pp - p_k;
     return fabs(dp) <= G.tol * pp || below_floor || at_noise;
   };
   // The first iteration runs for every interface as straight-line code; the
@@ -405,12 +421,27 @@ __device__ __forceinline__ Flux<T> riemann_flux(const Prim<T>& L, const Prim<T>&
   T gr, gu, gp, to;
   if constexpr (RS == 0) {
     // star velocity (average of the two sides' estimates) at the final p
-    const T XL = L.r * fma(G.half_gp1, p, aL);
-    const T XR = R.r * fma(G.half_gp1, p, aR);
-    const T iWL = fm::rsqrt(XL), iWR = fm::rsqrt(XR);
-    const T usL = L.u - (p - L.p) * iWL;
-    const T usR = R.u + (p - R.p) * iWR;
-    const T us = T(0.5) * (usL + usR);
+    T XL, XR, iWL, iWR, us;
+    if constexpr (!(sizeof(T) == 4 && CARRY)) {
+      XL = L.r * fma(G.half_gp1, p, aL);
+      XR = R.r * fma(G.half_gp1, p, aR);
+      iWL = fm::rsqrt(XL);
+      iWR = fm::rsqrt(XR);
+      const T usL = L.u - (p - L.p) * iWL;
+      const T usR = R.u + (p - R.p) * iWR;
+      us = T(0.5) * (usL + usR);
+    } else {
+      // FP32 (CARRY): from the last iterate p_k, u* to first order in the final step
+      // p - p_k (a converged step is within a few ulp of p, so the dropped
+      // second-order term is far below FP32 rounding) and the wave speeds as
+      // at p_k (relative change about half the step), instead of evaluating
+      // both sides again
+      XL = kXL;
+      XR = kXR;
+      iWL = kiWL;
+      iWR = kiWR;
+      us = T(0.5) * fma(kstep, kdus, kus);
+    }
 
     // upwind side of the contact (u* = 0 -> left)
     const bool left = us >= T(0);

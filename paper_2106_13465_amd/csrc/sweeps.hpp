@@ -18,26 +18,43 @@ namespace hydro {
 // ------------------------------------------------------------ wave helpers
 // Neighbour exchange by one lane (ds_bpermute through the LDS crossbar; the
 // DPP wavefront shifts measured slower on gfx950).  Edge lanes read their own
-// value; the x-sweep never uses those results.
-template <typename T>
-__device__ __forceinline__ T from_left(T v) {
-  return __shfl_up(v, 1);
+// value; the x-sweep never uses those results.  The byte addresses of the two
+// neighbours are computed once per kernel (Nbr) rather than at every exchange.
+struct Nbr {
+  int left, right;  // ds_bpermute addresses of lanes l - 1 and l + 1
+};
+__device__ __forceinline__ Nbr lane_neighbours() {
+  const int l = __lane_id();
+  return Nbr{(l > 0 ? l - 1 : l) * 4, (l < kWave - 1 ? l + 1 : l) * 4};
+}
+__device__ __forceinline__ float bpermute(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bpermute(int addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 template <typename T>
-__device__ __forceinline__ T from_right(T v) {
-  return __shfl_down(v, 1);
+__device__ __forceinline__ T from_left(const Nbr& nb, T v) {
+  return bpermute(nb.left, v);
 }
 template <typename T>
-__device__ __forceinline__ Prim<T> from_left(const Prim<T>& q) {
-  return Prim<T>{from_left(q.r), from_left(q.u), from_left(q.t), from_left(q.p)};
+__device__ __forceinline__ T from_right(const Nbr& nb, T v) {
+  return bpermute(nb.right, v);
 }
 template <typename T>
-__device__ __forceinline__ Prim<T> from_right(const Prim<T>& q) {
-  return Prim<T>{from_right(q.r), from_right(q.u), from_right(q.t), from_right(q.p)};
+__device__ __forceinline__ Prim<T> from_left(const Nbr& nb, const Prim<T>& q) {
+  return Prim<T>{from_left(nb, q.r), from_left(nb, q.u), from_left(nb, q.t), from_left(nb, q.p)};
 }
 template <typename T>
-__device__ __forceinline__ Flux<T> from_left(const Flux<T>& f) {
-  return Flux<T>{from_left(f.m), from_left(f.n), from_left(f.t), from_left(f.e)};
+__device__ __forceinline__ Prim<T> from_right(const Nbr& nb, const Prim<T>& q) {
+  return Prim<T>{from_right(nb, q.r), from_right(nb, q.u), from_right(nb, q.t),
+                 from_right(nb, q.p)};
+}
+template <typename T>
+__device__ __forceinline__ Flux<T> from_left(const Nbr& nb, const Flux<T>& f) {
+  return Flux<T>{from_left(nb, f.m), from_left(nb, f.n), from_left(nb, f.t), from_left(nb, f.e)};
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -138,17 +155,18 @@ __device__ __forceinline__ bool nonphysical(T r, T e) {
 // Flux at one interface with the starting guess the variant selects: the
 // network's correction of the two-rarefaction guess (GUESS; net is the
 // network staged in LDS) or that guess itself.  Called by all 64 lanes.
-template <int RS, bool SERIES, int GUESS, typename T>
+template <int RS, bool SERIES, int GUESS, bool CARRY = false, typename T>
 __device__ __forceinline__ Flux<T> interface_flux(const Prim<T>& L, const Prim<T>& R,
                                                   const Gas<T>& G, const Extras& ex,
                                                   const MlpInfer* net, int& iters, bool& conv,
                                                   bool& fb, T& pstar, bool& left) {
   if constexpr (GUESS != 0 && RS != 2)
-    return riemann_flux<RS, T, SERIES>(
+    return riemann_flux<RS, T, SERIES, CARRY>(
         L, R, G, LearnedGuess{net, ex.gamma, ex.gate_kappa, ex.gate_theta2}, iters, conv, fb,
         pstar, left);
   else
-    return riemann_flux<RS, T, SERIES>(L, R, G, NoLearnedGuess{}, iters, conv, fb, pstar, left);
+    return riemann_flux<RS, T, SERIES, CARRY>(L, R, G, NoLearnedGuess{}, iters, conv, fb, pstar,
+                                              left);
 }
 
 // A wave-uniform pointer moved to scalar registers (both halves read from the
@@ -276,15 +294,15 @@ struct Lane {
 // The x-sweep runs it along rows, the tiled y-sweep along columns of a tile
 // transposed through LDS.
 template <typename T, bool INSTR, int GUESS, int LIM, int RS, int NS>
-__device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& G,
+__device__ __forceinline__ void pencil_segment(Lane<T>& c, const Nbr& nb, T lam, const Gas<T>& G,
                                                const Extras& ex, const MlpInfer* net,
                                                DevState* st, bool iface_valid,
                                                unsigned long long log_key) {
   // COMPUTE: primitive variables, slopes, half-step face states
   T ir;
   const Prim<T> q = cons_to_prim(c.r, c.n, c.t, c.e, G, ir);
-  const Prim<T> ql = from_left(q);
-  const Prim<T> qr = from_right(q);
+  const Prim<T> ql = from_left(nb, q);
+  const Prim<T> qr = from_right(nb, q);
   Prim<T> dq;
   dq.r = limit<LIM>(q.r - ql.r, qr.r - q.r);
   dq.u = limit<LIM>(q.u - ql.u, qr.u - q.u);
@@ -297,28 +315,30 @@ __device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& 
   T xm = T(0), xp = T(0);
   if constexpr (NS > 0) {
     const T X = c.s * ir;
-    const T dX = limit<LIM>(X - from_left(X), from_right(X) - X);
+    const T dX = limit<LIM>(X - from_left(nb, X), from_right(nb, X) - X);
     const T hs = T(-0.5) * lam * q.u * dX;
     xm = X - T(0.5) * dX + hs;
     xp = X + T(0.5) * dX + hs;
   }
 
   // Riemann problem at this lane's right interface
-  const Prim<T> qm_next = from_right(qm);
+  const Prim<T> qm_next = from_right(nb, qm);
   int iters;
   bool conv, fb, left;
   T pstar;
   // FP64: the series form of the guess's power in smooth waves (measured
   // 4% faster on the x-sweep; no gain in FP32 or in the y-sweep's loop)
-  const Flux<T> F = interface_flux<RS, sizeof(T) == 8, GUESS>(qp, qm_next, G, ex, net, iters,
-                                                              conv, fb, pstar, left);
-  const Flux<T> Fl = from_left(F);  // the lane's left interface
+  // FP32: the final star state carried from the last Newton iterate (the
+  // registers are there in this one-cell-per-lane form)
+  const Flux<T> F = interface_flux<RS, sizeof(T) == 8, GUESS, sizeof(T) == 4>(
+      qp, qm_next, G, ex, net, iters, conv, fb, pstar, left);
+  const Flux<T> Fl = from_left(nb, F);  // the lane's left interface
   // scalar flux: mass flux times X on the side of the contact at x/t = 0
   T FX = T(0), FXl = T(0);
   if constexpr (NS > 0) {
-    const T xm_next = from_right(xm);
+    const T xm_next = from_right(nb, xm);
     FX = F.m * (left ? xp : xm_next);
-    FXl = from_left(FX);
+    FXl = from_left(nb, FX);
   }
 
   if (INSTR) {
@@ -338,6 +358,7 @@ __device__ __forceinline__ void pencil_segment(Lane<T>& c, T lam, const Gas<T>& 
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) void k_sweep_x(Batch<T> b, Gas<T> G, Extras ex) {
   const int lane = threadIdx.x & (kWave - 1);
+  const Nbr nb = lane_neighbours();
   // the learned guess's network, staged in LDS once per block
   __shared__ MlpInfer net_lds;
   const MlpInfer* net = nullptr;
@@ -388,7 +409,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
       // the right interfaces of its cells
       const bool valid = (lane >= 2 || (lane == 1 && x0 == 0)) && lane < 62 && i < d.nx;
       pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
-          c, lam, G, ex, net, st, valid,
+          c, nb, lam, G, ex, net, st, valid,
           ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
               ((unsigned long long)row * (d.nx + 1) + (i + 1)) * 2ull);
 
@@ -670,6 +691,7 @@ __device__ __forceinline__ int tile_col(int r, int c) {
 template <typename T, bool INSTR, int GUESS, int LIM, bool FUSE, int RS, int NS>
 __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_y_tile(Batch<T> b, Gas<T> G, Extras ex) {
   constexpr int NV = 4 + NS;
+  const Nbr nb = lane_neighbours();
   __shared__ T tile[NV][kTileRows][kTileCols];
   const int tid = threadIdx.x;
   // the learned guess's network, staged in LDS once per block
@@ -743,7 +765,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::t)) void k_sweep_
       const bool valid = (lane >= 2 || (lane == 1 && y0 == 0)) && lane < 62 && i < d.ny;
       const int x = x0 + cl;
       pencil_segment<T, INSTR, GUESS, LIM, RS, NS>(
-          c, lam, G, ex, net, st, valid,
+          c, nb, lam, G, ex, net, st, valid,
           ((unsigned long long)gi << 44) ^ ((unsigned long long)st->step << 24) ^
               (((unsigned long long)x * (d.ny + 1) + (i + 1)) * 2ull + 1ull));
       if (lane >= 2 && lane < 62 && i < d.ny) {
