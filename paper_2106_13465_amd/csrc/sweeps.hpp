@@ -256,9 +256,9 @@ constexpr int kOcc[8] = {HYDRO_OCC};  // x f64, x f64 learned, x f32, x f32 lear
 // (it spilled ~150 bytes per lane there); it asks for 2.  The HLLC FP32
 // y-sweep spilled 68 bytes at 6, the FP32 sweeps with a passive scalar 40-50;
 // they ask for 5.
-// The plain FP64 x-sweep (two-shock or HLLC, no scalar) is held at 5 waves:
-// 92 registers, no spill; left free, the allocator takes 98 and 4 waves.  With
-// the statistics or the fused max speed it spills at 5 and asks for 4.
+// The plain FP64 x-sweep (two-shock or HLLC, no scalar) asks for 5 waves and
+// fits 6 (77 registers); held at 7 it spills and runs 5% slower.  With the
+// statistics or the fused max speed it asks for 4.
 template <typename T, int GUESS, int RS, int NS, bool INSTR = false, bool FUSE = false>
 struct SweepOcc {
   static constexpr bool f32 = sizeof(T) == 4;
