@@ -36,11 +36,40 @@ KERNEL_SOURCES = ["paper_2106_13465_amd/csrc/kernels.hip", "paper_2106_13465_amd
                   "paper_2106_13465_amd/csrc/mlp.hpp"]
 
 
+def code_of(text: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed: the
+    part of a kernel source that the compiler turns into code (string and
+    character literals are kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code (comments and layout excluded), which
+    the committed counter summaries record: bench.py takes traffic and issue
+    figures from a summary only while it matches."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_of(f.read()).encode())
     return h.hexdigest()[:16]
 
 
