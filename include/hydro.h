@@ -431,6 +431,19 @@ int hydro_batch_set_logger(hydro_batch_t *b, float *records, long long capacity,
                            unsigned long long seed, double rate_smooth, double rate_strong);
 long long hydro_batch_logger_count(hydro_batch_t *b);
 
+/* ------------------------------------------------------------------------
+ * Measurement: the bandwidth a plain streaming kernel reaches on this GPU,
+ * the practical ceiling beside the published HBM peak for the sweeps, which
+ * read and write their state once per sweep (measured in bench.py).
+ * ------------------------------------------------------------------------ */
+/* Copy nbytes from src to dst (device memory owned by the caller, both
+ * 16-byte aligned, not overlapping), asynchronously on hip_stream: one 8 KiB
+ * chunk per block, 16-byte nontemporal loads and stores.  nbytes must be
+ * a multiple of 16 (0 is a no-op).  HYDRO_EINVAL for a NULL pointer, a
+ * misaligned pointer or size, or overlapping ranges; HYDRO_EDEVICE if the
+ * launch fails. */
+int hydro_stream_copy(void *dst, const void *src, long long nbytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,6 +109,8 @@ SIGNATURES = {
     "hydro_step_noalloc": (ctypes.c_int, [ctypes.c_int, _I, _I, _I, _LL, _L, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _vp,
                                           _vp]),
+    # measurement: streaming copy
+    "hydro_stream_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_longlong, _vp]),
     # learned guess
     "hydro_mlp_dev_bytes": (ctypes.c_size_t, []),
     "hydro_mlp_pack": (ctypes.c_int, [_vp, _vp, _vp]),

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libhydro.so")
 # (source, floating-point contraction)
 SOURCES = [("api.cpp", "off"), ("plan.cpp", "off"), ("kernels.hip", "fast"),
            ("kernels_scalar.hip", "fast"), ("mlp_kernels.hip", "fast"),
-           ("noalloc.hip", "off")]
+           ("noalloc.hip", "off"), ("stream_copy.hip", "off")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

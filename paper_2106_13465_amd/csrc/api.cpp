@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -532,6 +533,19 @@ size_t hydro_mlp_dev_bytes(void) { return sizeof(hydro::MlpDev); }
 
 size_t hydro_mlp_grad_scratch_bytes(long long n) {
   return sizeof(float) * hydro::mlp_grad_scratch_floats(n < 1 ? 1 : n);
+}
+
+int hydro_stream_copy(void* dst, const void* src, long long nbytes, void* hip_stream) {
+  if (!dst || !src) return fail(HYDRO_EINVAL, "NULL argument");
+  if (nbytes < 0 || nbytes % 16 != 0) return fail(HYDRO_EINVAL, "nbytes %lld", nbytes);
+  const uintptr_t d = reinterpret_cast<uintptr_t>(dst), s = reinterpret_cast<uintptr_t>(src);
+  if (d % 16 != 0 || s % 16 != 0) return fail(HYDRO_EINVAL, "pointers not 16-byte aligned");
+  if (nbytes == 0) return HYDRO_OK;
+  if (d < s + (uintptr_t)nbytes && s < d + (uintptr_t)nbytes)
+    return fail(HYDRO_EINVAL, "overlapping ranges");
+  hipError_t e = hydro::launch_stream_copy(dst, src, nbytes / 16, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(e, "hydro_stream_copy");
+  return HYDRO_OK;
 }
 
 int hydro_mlp_pack(const float* params, void* mlp, void* stream) {

@@ -37,6 +37,8 @@ hipError_t launch_copy(const Batch<T>& b, hipStream_t s);
 template <typename T>
 hipError_t launch_totals(const Batch<T>& b, int total_blocks, double* partials, hipStream_t s);
 
+// Streaming copy of n16 16-byte words (n16 > 0; both pointers 16-byte aligned).
+hipError_t launch_stream_copy(void* dst, const void* src, long long n16, hipStream_t s);
 hipError_t launch_reset_acc(DevState* st, int n, hipStream_t s);
 hipError_t launch_finalize_dt(const GridDesc* g, DevState* st, int n, bool advance, bool reset,
                               hipStream_t s);

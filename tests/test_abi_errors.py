@@ -99,3 +99,22 @@ def test_create_without_gpu_fails_cleanly(lib):
     h = lib.hydro_create(8, 8, 1.4, 0.8, 3)
     assert not h
     assert err()  # a device error with the runtime's message
+
+
+def test_stream_copy_validation(lib):
+    """hydro_stream_copy rejects NULL, misaligned or overlapping arguments and
+    sizes that are not whole 16-byte words before touching any memory (the
+    addresses below are never dereferenced); 0 bytes is a no-op."""
+    vp = ctypes.c_void_p
+    assert lib.hydro_stream_copy(None, vp(4096), 16, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_stream_copy(vp(4096), None, 16, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_stream_copy(vp(4096), vp(8192), 24, None) == _lib.HYDRO_EINVAL
+    assert "nbytes" in err()
+    assert lib.hydro_stream_copy(vp(4096), vp(8192), -16, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_stream_copy(vp(4104), vp(8192), 16, None) == _lib.HYDRO_EINVAL
+    assert "aligned" in err()
+    assert lib.hydro_stream_copy(vp(4096), vp(8200), 16, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_stream_copy(vp(4096), vp(4096 + 32), 64, None) == _lib.HYDRO_EINVAL
+    assert "overlap" in err()
+    assert lib.hydro_stream_copy(vp(4096 + 32), vp(4096), 64, None) == _lib.HYDRO_EINVAL
+    assert lib.hydro_stream_copy(vp(4096), vp(8192), 0, None) == _lib.HYDRO_OK
