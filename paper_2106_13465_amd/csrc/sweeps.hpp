@@ -475,8 +475,11 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
     const int y0 = sg * b.seg;
     const int y1 = min(y0 + b.seg, d.ny);
     const T lam = T(st->dt / d.h);
-    // the grid's variable planes in scalar registers, rows added to them as
-    // scalar offsets, the lane's column as one 32-bit byte offset
+    // the grid's variable planes from scalar registers and the lane's column
+    // as a 32-bit byte offset (the compiler folds the two into one 64-bit
+    // address per plane and lane once per work item and adds each row's
+    // offset to it; rows through buffer descriptors, which keep that addition
+    // scalar, timed no better)
     const auto in0 = uniform_ptr(b.src + d.off), in1 = uniform_ptr(b.src + d.off + P);
     const auto in2 = uniform_ptr(b.src + d.off + 2 * P), in3 = uniform_ptr(b.src + d.off + 3 * P);
     const auto out0 = uniform_ptr(b.dst + d.off), out1 = uniform_ptr(b.dst + d.off + P);
