@@ -8,6 +8,12 @@
  * primitive variables, Riemann problems at the interfaces, incoming fluxes,
  * update), with the numerical readings the paper leaves open stated where
  * they are taken.
+ *
+ * Parity unpinned: the state the two-shock solver's sampling takes inside a
+ * transonic rarefaction fan (a reading: linear interpolation across the fan,
+ * in oracle_riemann) has no closed form to pin it to; it is checked only by
+ * its continuity at the fan's edges and by the convergence of the random
+ * shock-tube family.  Every other function is pinned by tests/.
  */
 #include "hydro_oracle.h"
 
@@ -214,7 +220,8 @@ int oracle_riemann(const double qL[4], const double qR[4], double gamma,
     sin_ = cs - s * us;
   }
 
-  /* state at x/t = 0 (reading: linear interpolation across a fan) */
+  /* state at x/t = 0 (reading: linear interpolation across a fan; parity
+     unpinned inside a transonic fan, see the header) */
   if (sout < 0.0) {
     qg[0] = ro;
     qg[1] = uo;
