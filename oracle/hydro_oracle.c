@@ -9,11 +9,12 @@
  * update), with the numerical readings the paper leaves open stated where
  * they are taken.
  *
- * Parity unpinned: the state the two-shock solver's sampling takes inside a
- * transonic rarefaction fan (a reading: linear interpolation across the fan,
- * in oracle_riemann) has no closed form to pin it to; it is checked only by
- * its continuity at the fan's edges and by the convergence of the random
- * shock-tube family.  Every other function is pinned by tests/.
+ * The state the two-shock solver's sampling takes inside a transonic
+ * rarefaction fan (a reading: linear interpolation across the fan, in
+ * oracle_riemann) is pinned against the exact fan: on families of weak
+ * transonic rarefactions it must differ from the exact state by the
+ * closed-form error of linear interpolation at x/t = 0, second order in the
+ * fan width (tests/test_oracle_riemann.py).
  */
 #include "hydro_oracle.h"
 
@@ -220,8 +221,7 @@ int oracle_riemann(const double qL[4], const double qR[4], double gamma,
     sin_ = cs - s * us;
   }
 
-  /* state at x/t = 0 (reading: linear interpolation across a fan; parity
-     unpinned inside a transonic fan, see the header) */
+  /* state at x/t = 0 (reading: linear interpolation across a fan) */
   if (sout < 0.0) {
     qg[0] = ro;
     qg[1] = uo;

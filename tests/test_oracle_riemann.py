@@ -320,3 +320,45 @@ def test_floor_is_the_star_pressure_below_it(orc):
     qL, qR = prim_state(1.0, -0.5, 0.0, 1.0), prim_state(0.5, 0.5, 0.0, 0.8)
     _, p, _, it, conv = orc.riemann(qL, qR, G)
     assert conv and p > 100 * pmin
+
+
+def test_transonic_fan_state_is_the_linear_interpolation_of_the_exact_fan(orc):
+    """Pin of the two-shock sampling inside a transonic rarefaction fan (the
+    linear-interpolation reading).  Families of left rarefactions of strength
+    eps = 1 - p*/p_L, built so that the exact fan spans x/t in
+    [-theta w, (1 - theta) w] (no right wave: the right state is the star
+    state), are sampled at x/t = 0.  In the exact fan u is linear in x/t while
+    rho and p are powers of the fan sound speed
+    c(x/t) = 2/(gamma+1) (c_L + (gamma-1)/2 (u_L - x/t)), so the interpolated
+    state must differ from the exact one, to leading order, by the error of
+    linear interpolation at that point, theta (1 - theta) w^2 / 2 f''(0),
+    positive for the convex rho and p: second order in eps with that constant.
+    Off-centre points (theta != 1/2) tell the weight from its complement;
+    a wrong edge speed or interpolation in other variables changes the order
+    or the constant."""
+    g = G
+    z = (g - 1) / (2 * g)
+    cL = math.sqrt(g)
+    dc = (g - 1) / (g + 1)  # |dc/d(x/t)| in the fan
+    a, b = 2.0 / (g - 1), 2.0 * g / (g - 1)  # rho ~ c^a, p ~ c^b
+    for theta in (0.25, 0.7):
+        errs = []
+        for eps in (0.04, 0.02, 0.01, 0.005):
+            ps = 1.0 - eps
+            cs = cL * ps**z
+            w = (g + 1) / (g - 1) * (cL - cs)  # fan width
+            uL = cL - theta * w  # head at -theta w, tail at (1 - theta) w
+            us = uL + 2.0 / (g - 1) * (cL - cs)
+            qg, *_ = orc.riemann(prim_state(1.0, uL, 0.0, 1.0), prim_state(0.5, us, 0.0, ps), G)
+            rho_x, u_x, p_x = ex.sample((1.0, uL, 1.0), (0.5, us, ps), 0.0, g)
+            c0 = 2.0 / (g + 1) * (cL + (g - 1) / 2 * uL)  # exact c at x/t = 0
+            k = theta * (1 - theta) * w * w / 2
+            rho2 = a * (a - 1) * (c0 / cL) ** (a - 2) * (dc / cL) ** 2
+            p2 = b * (b - 1) * (c0 / cL) ** (b - 2) * (dc / cL) ** 2
+            e_rho, e_p = qg[0] - rho_x, qg[3] - p_x
+            assert math.isclose(e_rho, k * rho2, rel_tol=0.08), (theta, eps, e_rho, k * rho2)
+            assert math.isclose(e_p, k * p2, rel_tol=0.08), (theta, eps, e_p, k * p2)
+            assert abs(qg[1] - u_x) < 0.05 * abs(e_rho)  # u: linear in x/t, higher order
+            errs.append(e_rho)
+        rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+        assert all(1.9 < r < 2.1 for r in rates), (theta, rates)
