@@ -415,3 +415,58 @@ def test_checkpoint_restart_bitwise(torch_cuda, orc):
     c.step(4)
     assert np.array_equal(c.get_state(), full)
     assert c.clock()[1] == 8 and abs(c.clock()[0] - a.clock()[0]) <= 1e-15 * a.clock()[0]
+
+
+def transonic_fans(n_along, n_across, axis):
+    """Rows (axis 0: the jump along x) or columns (axis 1: along y) each
+    holding one Riemann problem whose left wave is a transonic rarefaction:
+    strength eps = 1 - p*/p_L from 0.005 to 0.3 and the sonic point at a
+    fraction theta of the fan from 0.1 to 0.9 (the right state is the star
+    state, so there is no right wave).  Uniform states on either side of the
+    jump, so the limited slopes vanish there and the interface at the jump
+    sees exactly (L, R): every pencil exercises the fan sampling."""
+    g = 1.4
+    z = (g - 1) / (2 * g)
+    cL = math.sqrt(g)
+    U = np.empty((4, n_across, n_along) if axis == 0 else (4, n_along, n_across))
+    for k, (eps, theta) in enumerate(zip(np.geomspace(0.005, 0.3, n_across),
+                                         np.linspace(0.1, 0.9, n_across))):
+        ps = 1.0 - eps
+        cs = cL * ps**z
+        w = (g + 1) / (g - 1) * (cL - cs)
+        uL = cL - theta * w
+        us = uL + 2.0 / (g - 1) * (cL - cs)
+        left = inputs.conservative(1.0, uL, 0.1, 1.0)
+        right = inputs.conservative(0.5, us, -0.2, ps)
+        half = n_along // 2
+        pencil = np.empty((4, n_along))
+        pencil[:, :half] = np.asarray(left).reshape(4, 1)
+        pencil[:, half:] = np.asarray(right).reshape(4, 1)
+        if axis == 0:
+            U[:, k, :] = pencil
+        else:  # normal momentum is the y component
+            U[:, :, k] = pencil[[0, 2, 1, 3]]
+    return U
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_transonic_fans_fp64(torch_cuda, orc, direction):
+    """Every pencil's middle interface is a transonic rarefaction (the
+    sampling's fan branch, pinned on the oracle against the exact fan): one
+    sweep in either direction matches the oracle to the FP64 bar, and a
+    second-order step of each precision stays close to it."""
+    U = transonic_fans(130, 64, direction)
+    print(f"transonic fans dir={direction} shape={U.shape}", flush=True)
+    h = make(torch_cuda, U, 2)
+    c = orc.cfg(bc=2)
+    dt = h.compute_dt()
+    h.sweep(direction)
+    ref = U.copy()
+    orc.sweep(ref, direction, dt, c)
+    assert rel_err(h.get_state(), ref) <= TOL64
+    h32 = make(torch_cuda, U, 2, dtype=torch_cuda.float32)
+    h32.compute_dt()
+    h32.sweep(direction)
+    got = h32.get_state().astype(np.float64)
+    for k in range(4):
+        assert np.abs(got[k] - ref[k]).sum() <= 1e-5 * np.abs(ref[k]).sum(), k
