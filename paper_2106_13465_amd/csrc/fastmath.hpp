@@ -110,6 +110,26 @@ __device__ __forceinline__ float root_inv(float x, int k, float inv_k) {
   return exp2(-inv_k * log2(x));
 }
 
+// (a/b)^(-1/k) for positive normal a, b within the FP32 range (pressures:
+// floored, finite) and x = a/b computed by the caller in FP64: an FP32 seed
+// 2^(-(log2 a - log2 b)/k) from the two FP32 logarithms (no range reduction
+// needed: a and b are FP32 numbers even where their ratio is not) and one
+// FP64 Newton step on x y^k = 1.  The seed's relative error is about 1e-7
+// times max(1, |log2 a|, |log2 b|) / k, and the step squares it (below
+// 3e-12 for pressures in 1e-20..1e20), ample for a starting guess.
+__device__ __forceinline__ double root_inv_ratio(double a, double b, double x, int k,
+                                                 double inv_k) {
+  const float la = __builtin_amdgcn_logf((float)a), lb = __builtin_amdgcn_logf((float)b);
+  const double y0 = (double)__builtin_amdgcn_exp2f((lb - la) * (float)inv_k);
+  const double t = fma(x, ipow(y0, k), -1.0);
+  return fma(-y0 * inv_k, t, y0);
+}
+__device__ __forceinline__ float root_inv_ratio(float a, float b, float x, int k, float inv_k) {
+  (void)a;
+  (void)b;
+  return root_inv(x, k, inv_k);
+}
+
 // x^(-1/k) to full precision (the exact Riemann solver's wave curves, where
 // the power enters the result rather than a starting guess): a second Newton
 // step after root_inv takes the ~k 1e-14 error to rounding level.

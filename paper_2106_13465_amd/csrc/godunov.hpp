@@ -227,7 +227,8 @@ __device__ __forceinline__ T two_rarefaction_guess(const Prim<T>& L, const Prim<
     if (SERIES && __ballot(!(fabs(e) <= T(kSeriesEps))) == 0ull)
       xz = fma(e, fma(e, fma(e, fma(e, G.ser[3], G.ser[2]), G.ser[1]), G.ser[0]), T(1));
     else
-      xz = G.ipow_k > 0 ? fm::root_inv(x, G.ipow_k, G.z) : fm::pow_pos(x, -G.z);
+      xz = G.ipow_k > 0 ? fm::root_inv_ratio(R.p, L.p, x, G.ipow_k, G.z)
+                        : fm::pow_pos(x, -G.z);
     const T den = cL + cR * xz;
     const T ratio = num * fm::rcp(den);
     q = L.p * (G.ipow_k > 0 ? fm::ipow(ratio, G.ipow_k) : fm::pow_pos(ratio, G.inv_z));
