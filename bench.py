@@ -165,7 +165,7 @@ def sweep_record(cells, elem, phase, nv=4):
 def copy_bandwidth(nbytes: int, reps: int = 10) -> dict:
     """GB/s of a plain device-to-device copy of nbytes (nbytes read and nbytes
     written, timed with HIP events on one stream): the library's streaming
-    copy kernel (hydro_stream_copy: 16-byte loads, nontemporal stores) and
+    copy kernel (hydro_stream_copy: 8 KiB per block, nontemporal loads and stores) and
     torch's copy, the bandwidth a streaming kernel reaches on this GPU for a
     transfer as large as one sweep's."""
     import ctypes

@@ -438,7 +438,7 @@ long long hydro_batch_logger_count(hydro_batch_t *b);
  * ------------------------------------------------------------------------ */
 /* Copy nbytes from src to dst (device memory owned by the caller, both
  * 16-byte aligned, not overlapping), asynchronously on hip_stream: one 8 KiB
- * chunk per block, 16-byte nontemporal loads and stores.  nbytes must be
+ * chunk per block, 4-byte nontemporal loads and stores.  nbytes must be
  * a multiple of 16 (0 is a no-op).  HYDRO_EINVAL for a NULL pointer, a
  * misaligned pointer or size, or overlapping ranges; HYDRO_EDEVICE if the
  * launch fails. */

@@ -19,6 +19,8 @@ namespace hydro {
 constexpr int kMaxIter = 32;      // largest Newton cap (HYDRO_MAX_NITER)
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kXOut = kWave - 4;  // x-sweep cells updated per 64-lane segment
+constexpr int kXRing = 128;       // x-sweep store ring per wave and variable (> 63 + kXOut)
+static_assert(kXRing >= 63 + kXOut && (kXRing & (kXRing - 1)) == 0, "ring size");
 constexpr int kWavesPerBlock = 4;
 constexpr int kTileCols = 16;        // tiled y-sweep: columns per tile
 constexpr int kTileRows = kWave;     // ... rows held per tile (one per lane)

@@ -527,7 +527,7 @@ hipError_t Plan::autotune(hydro_tune_t* out, bool use_cache) {
       return hipSuccess;
     };
     const unsigned persist[] = {0u, (unsigned)(cus * 2), (unsigned)(cus * 4), (unsigned)(cus * 8)};
-    const int segx[] = {1, 2, 4, 8};
+    const int segx[] = {1, 2, 4, 8, 16};
     std::vector<int> segy = {32, 64, 128, 256, 512};
     int maxny = 0;
     for (int g = 0; g < n; ++g) maxny = std::max(maxny, ny[g]);

@@ -366,6 +366,22 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
     mlp_stage(ex.mlp, &net_lds);
     net = &net_lds;
   }
+  // Line-aligned stores (the variants without passive scalars or learned
+  // guess): a segment updates 60 cells, so its stores would start and end
+  // inside 128-byte lines, and partial-line stores cost HBM time of their own
+  // (a four-plane copy with every 64-cell store shifted by two cells takes
+  // 10-13% longer than the aligned one, and more with streaming stores).  Each
+  // wave therefore parks its updated cells in a ring of kXRing cells per
+  // variable in LDS and stores whole 64-cell blocks, aligned to the output
+  // address, with streaming stores; the rest of the work item's last block
+  // goes out at its end (long items, seg_x 8-16, keep those few).  The ring
+  // holds at most 63 + 60 pending cells.  A wave reads back only what it wrote
+  // itself, and LDS executes a wave's instructions in order, so no barrier is
+  // needed, only a fence against the compiler moving the LDS accesses across
+  // each other.
+  constexpr bool STAGE = (NS == 0 && GUESS == 0);
+  __shared__ T ring[STAGE ? kWavesPerBlock : 1][4][kXRing];
+  T(*const wring)[kXRing] = ring[STAGE ? threadIdx.x / kWave : 0];
   for (long long w = first_wave(); w < b.items; w += wave_stride()) {
     const int gi = find_grid<Key::X>(b.g, b.ngrids, w);
     const GridDesc d = load_desc(b.g, gi);
@@ -386,6 +402,27 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
     const auto out2 = uniform_ptr(outp + 2 * P), out3 = uniform_ptr(outp + 3 * P);
     int status = 0;
     T smax = T(0);  // max wave speed of the written cells (FUSE)
+    // STAGE: cells [flushed, produced) of the row are parked in the ring; block
+    // boundaries are where the output address is a multiple of 64 cells
+    int flushed = seg0 * kXOut;
+    const int xa = (int)(((unsigned long long)outp / sizeof(T)) & 63u);
+    auto flush = [&](int produced, bool last) {
+      while (flushed < produced) {
+        const int bs = ((flushed + xa) & ~63) - xa;
+        const int lim = min(bs + 64, produced);
+        if (lim < bs + 64 && !last) break;
+        const int cell = bs + lane;
+        if (cell >= flushed && cell < lim) {
+          const int k = cell & (kXRing - 1);
+          const unsigned oo = (unsigned)cell * (unsigned)sizeof(T);
+          __builtin_nontemporal_store(wring[0][k], ptr_at(out0, oo));
+          __builtin_nontemporal_store(wring[1][k], ptr_at(out1, oo));
+          __builtin_nontemporal_store(wring[2][k], ptr_at(out2, oo));
+          __builtin_nontemporal_store(wring[3][k], ptr_at(out3, oo));
+        }
+        flushed = lim;
+      }
+    };
 
     for (int sgi = 0; sgi < b.seg; ++sgi) {
       const int seg = seg0 + sgi;
@@ -415,15 +452,32 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
 
       // WRITE: cells x0 .. x0+59
       if (lane >= 2 && lane < 62 && i < d.nx) {
-        const unsigned oo = (unsigned)i * (unsigned)sizeof(T);
-        *ptr_at(out0, oo) = c.r;
-        *ptr_at(out1, oo) = c.n;
-        *ptr_at(out2, oo) = c.t;
-        *ptr_at(out3, oo) = c.e;
-        if constexpr (NS > 0) outp[4 * P + i] = c.s;
+        if constexpr (STAGE) {
+          const int k = i & (kXRing - 1);
+          wring[0][k] = c.r;
+          wring[1][k] = c.n;
+          wring[2][k] = c.t;
+          wring[3][k] = c.e;
+        } else {
+          const unsigned oo = (unsigned)i * (unsigned)sizeof(T);
+          *ptr_at(out0, oo) = c.r;
+          *ptr_at(out1, oo) = c.n;
+          *ptr_at(out2, oo) = c.t;
+          *ptr_at(out3, oo) = c.e;
+          if constexpr (NS > 0) outp[4 * P + i] = c.s;
+        }
         status |= nonphysical(c.r, c.e) ? kStatusNonPhys : 0;
         if constexpr (FUSE) smax = fmax(smax, max_speed(c.r, c.n, c.t, c.e, G));
       }
+      if constexpr (STAGE) {
+        __builtin_amdgcn_wave_barrier();
+        flush(min(x0 + kXOut, d.nx), false);
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if constexpr (STAGE) {
+      flush(min((seg0 + b.seg) * kXOut, d.nx), true);
+      __builtin_amdgcn_wave_barrier();
     }
     if (status) atomicOr(&st->status, status);
     if constexpr (FUSE) {
@@ -639,7 +693,9 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS>::y)) void k_sweep_
           if (xin) {
             const long long off = (long long)j * pitch;
             // streaming stores: the next sweep reads these only after the
-            // whole grid (measured faster for the y-sweep, slower for the x-sweep)
+            // whole grid (faster here; the x-sweep streams only whole aligned
+            // blocks, since streaming stores that start or end inside a line
+            // are slower than plain ones)
             __builtin_nontemporal_store(nr, ptr_at(out0 + off, xo_out));
             __builtin_nontemporal_store(nt, ptr_at(out1 + off, xo_out));
             __builtin_nontemporal_store(nn, ptr_at(out2 + off, xo_out));
