@@ -161,6 +161,50 @@ def test_segments_do_not_change_results(torch_cuda, orc):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("pitch", [1001, 1013])
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_staged_stores_any_row_alignment(torch_cuda, orc, dtype_name, pitch):
+    """The x-sweep parks updated cells in LDS and stores whole 64-cell blocks
+    aligned to the output address.  Rows of 1001 cells (16 whole segments and
+    a partial one) at a pitch that gives every row another alignment, and work
+    items of 1, 2, 7 and 16 segments (item ends inside a block, a last item
+    running past the row's end): one x-sweep gives the same bits for every
+    segment count and matches the oracle (FP64 to the bar, FP32 by relative
+    L1).  With the pitch equal to the row length a store past a row's end
+    would land in the next row; with padding, the padding stays untouched."""
+    from paper_2106_13465_amd.hydro import Hydro
+
+    dt = getattr(torch_cuda, dtype_name)
+    nx, ny = 1001, 23
+    U = inputs.random_states(nx, ny, seed=57, rough=0.5)
+    c = orc.cfg(bc=3)
+    outs = []
+    for sx in (1, 2, 7, 16):
+        print(f"staged stores {dtype_name} seg_x={sx} nx={nx} pitch={pitch}", flush=True)
+        h = Hydro(nx, ny, 1.4, 0.8, 3, dtype=dt, pitch=pitch)
+        h.set_options(seg_x=sx)
+        h.set_state(U)
+        h.U[:, :, nx:] = -7.0
+        torch_cuda.cuda.synchronize()
+        dt_gpu = h.compute_dt()
+        h.sweep(0)
+        h.stream.synchronize()
+        full = h.U.cpu().numpy()
+        assert np.all(full[:, :, nx:] == -7.0)
+        outs.append(full)
+        h.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ref = U.copy()
+    orc.sweep(ref, 0, dt_gpu, c)
+    got = outs[0][:, :, :nx].astype(np.float64)
+    if dtype_name == "float64":
+        assert rel_err(got, ref) <= TOL64
+    else:
+        for k in range(4):
+            assert np.sum(np.abs(got[k] - ref[k])) <= 1e-5 * np.sum(np.abs(ref[k]))
+
+
 def test_stats_counts(torch_cuda, orc):
     U = inputs.random_states(130, 70, seed=42)
     h = make(torch_cuda, U, 2, stats=1)
