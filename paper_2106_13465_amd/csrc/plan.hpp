@@ -15,7 +15,8 @@ namespace hydro {
 
 // Launch shape of the two sweeps; results do not depend on it.
 struct LaunchCfg {
-  int seg_x = 1;          // 60-cell segments per x-sweep item
+  int seg_x = 8;          // 60-cell segments per x-sweep item (long items keep the
+                          // x-sweep's staged stores line-aligned)
   int seg_y = 128;        // rows per y-sweep item
   unsigned blocks_x = 0;  // 0: one block per 4 items; else persistent
   unsigned blocks_y = 0;
