@@ -379,6 +379,7 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
   // itself, and LDS executes a wave's instructions in order, so no barrier is
   // needed, only a fence against the compiler moving the LDS accesses across
   // each other.
+  // (The block has at most kWavesPerBlock waves: __launch_bounds__(256).)
   constexpr bool STAGE = (NS == 0 && GUESS == 0);
   __shared__ T ring[STAGE ? kWavesPerBlock : 1][4][kXRing];
   T(*const wring)[kXRing] = ring[STAGE ? threadIdx.x / kWave : 0];
@@ -403,7 +404,9 @@ __global__ __launch_bounds__(256, (SweepOcc<T, GUESS, RS, NS, INSTR, FUSE>::x)) 
     int status = 0;
     T smax = T(0);  // max wave speed of the written cells (FUSE)
     // STAGE: cells [flushed, produced) of the row are parked in the ring; block
-    // boundaries are where the output address is a multiple of 64 cells
+    // boundaries are where the first variable's output address is a multiple
+    // of 64 cells (the other planes share it when the plane stride is a
+    // multiple of 64 cells; otherwise only their speed suffers)
     int flushed = seg0 * kXOut;
     const int xa = (int)(((unsigned long long)outp / sizeof(T)) & 63u);
     auto flush = [&](int produced, bool last) {
