@@ -124,8 +124,10 @@ typedef struct {
   int guess;     /* HYDRO_GUESS_PTR or HYDRO_GUESS_MLP (needs hydro_set_mlp)*/
   int stats;     /* nonzero: count Newton iterations per interface         */
   int seg_x;     /* x-sweep: consecutive 60-cell wave segments per wave;
-                    0 = library default                                    */
-  int seg_y;     /* y-sweep: cells per marching thread; 0 = default        */
+                    0 = library default (8; hydro_autotune picks among
+                    1, 2, 4, 8, 16).  Results do not depend on it.          */
+  int seg_y;     /* y-sweep: cells per marching thread; 0 = default (128);
+                    results do not depend on it                            */
   double learned_gate; /* with HYDRO_GUESS_MLP: strength s above which an
                     interface takes the learned guess; the others keep the
                     two-rarefaction guess, and a wave evaluates the network
